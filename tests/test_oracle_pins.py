@@ -1,0 +1,550 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the pin it realises (algebraic identity, invariant, closed
+form, brute force, printed special case).  None of them re-derives a
+quantity with the oracle's own formula.
+"""
+from fractions import Fraction
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import lbm_oracle as O
+
+RNG = np.random.default_rng(12345)
+
+
+def _tc():
+    return O.critical_temperature(O.Params(1, 1, 1))
+
+
+# ---------------------------------------------------------------- lattices
+
+def _frac_det(m):
+    a = [[Fraction(int(v)) for v in row] for row in m]
+    n = len(a)
+    det = Fraction(1)
+    for c in range(n):
+        piv = next(r for r in range(c, n) if a[r][c] != 0)
+        if piv != c:
+            a[c], a[piv] = a[piv], a[c]
+            det = -det
+        det *= a[c][c]
+        for r in range(c + 1, n):
+            fac = a[r][c] / a[c][c]
+            for k in range(c, n):
+                a[r][k] -= fac * a[c][k]
+    return det
+
+
+def test_d3q19_velocity_set_is_the_standard_one():
+    """Brute force: the 19 vectors of {-1,0,1}^3 with |c|^2 <= 2, each once,
+    rest first, then the 6 axes, then the 12 face diagonals; opposite pairs
+    adjacent (1,2), (3,4), ... (17,18)."""
+    allv = {c for c in itertools.product((-1, 0, 1), repeat=3) if sum(x * x for x in c) <= 2}
+    got = [tuple(int(x) for x in c) for c in O.C19]
+    assert set(got) == allv and len(got) == 19
+    assert got[0] == (0, 0, 0)
+    assert all(sum(x * x for x in c) == 1 for c in got[1:7])
+    assert all(sum(x * x for x in c) == 2 for c in got[7:])
+    for i in range(1, 19, 2):
+        assert O.OPP19[i] == i + 1 and O.OPP19[i + 1] == i
+
+
+def test_mhat_rows_are_monomials_of_the_velocities():
+    """(A.1): the rows are 1, x, y, z, |c|^2, 2x^2-y^2-z^2, y^2-z^2, xy, xz, yz,
+    x^2y, xy^2, x^2z, xz^2, y^2z, yz^2, x^2y^2, x^2z^2, y^2z^2 at c_i."""
+    x, y, z = O.C19[:, 0], O.C19[:, 1], O.C19[:, 2]
+    mono = [np.ones(19, int), x, y, z, x * x + y * y + z * z, 2 * x * x - y * y - z * z,
+            y * y - z * z, x * y, x * z, y * z, x * x * y, x * y * y, x * x * z, x * z * z,
+            y * y * z, y * z * z, x * x * y * y, x * x * z * z, y * y * z * z]
+    assert np.array_equal(np.array(mono), O.MHAT)
+
+
+def test_m7_rows_are_monomials_and_velocities():
+    """(A.2): rows 1, x, y, z, |c|^2, x^2-y^2, x^2-z^2 over rest + 6 axes."""
+    allv = {c for c in itertools.product((-1, 0, 1), repeat=3) if sum(x * x for x in c) <= 1}
+    got = [tuple(int(v) for v in c) for c in O.C7]
+    assert set(got) == allv
+    x, y, z = O.C7[:, 0], O.C7[:, 1], O.C7[:, 2]
+    mono = [np.ones(7, int), x, y, z, x * x + y * y + z * z, x * x - y * y, x * x - z * z]
+    assert np.array_equal(np.array(mono), O.M7)
+
+
+def test_transform_determinants_and_inverses():
+    """Exact rational determinants (both transforms invertible) and M M^-1 = I."""
+    assert _frac_det(O.MHAT) == -196608
+    assert _frac_det(O.M7) == -24
+    assert np.allclose(O.MHAT_F @ O.MHAT_INV, np.eye(19), atol=1e-14)
+    assert np.allclose(O.M7_F @ O.M7_INV, np.eye(7), atol=1e-14)
+
+
+def test_d3q19_weights_isotropy():
+    """Sec. 2.1 weights: sum 1, second moment c_s^2 I, fourth moment
+    c_s^4 (d_ab d_cd + d_ac d_bd + d_ad d_bc), odd moments 0."""
+    w, c = O.W19, O.C19.astype(float)
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, c, c), np.eye(3) / 3, atol=1e-15)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    d = np.eye(3)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.allclose(m4, iso, atol=1e-15)
+    assert np.allclose(np.einsum("i,ia->a", w, c), 0)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, c, c, c), 0)
+
+
+# ---------------------------------------------------------------- equilibria
+
+def test_meq_rows_0_15_equal_transform_of_feq_and_offset_of_16_18():
+    """eq. (10) against M (A.1) applied to eq. (2): rows 0-15 agree exactly;
+    rows 16-18 differ by rho (u_a^2 + u_b^2)/6 (the documented reading)."""
+    rho = RNG.uniform(0.2, 7.0, 50)
+    u = RNG.uniform(-0.2, 0.2, (3, 50))
+    mf = O.MHAT_F @ O.feq19(rho, u)
+    me = O.meq19(rho, u)
+    assert np.allclose(mf[:16], me[:16], rtol=1e-14, atol=1e-14)
+    off = mf[16:] - me[16:]
+    ux, uy, uz = u
+    expect = np.stack([rho * (ux**2 + uy**2), rho * (ux**2 + uz**2), rho * (uy**2 + uz**2)]) / 6
+    assert np.allclose(off, expect, rtol=1e-12, atol=1e-15)
+
+
+def test_feq_moments_closed_form():
+    """eq. (2): sum f = rho, sum c f = rho u, sum c c f = rho (c_s^2 I + u u)."""
+    rho = RNG.uniform(0.2, 7.0, 20)
+    u = RNG.uniform(-0.2, 0.2, (3, 20))
+    f = O.feq19(rho, u)
+    c = O.C19.astype(float)
+    assert np.allclose(f.sum(0), rho)
+    assert np.allclose(c.T @ f, rho * u)
+    P = np.einsum("ia,ib,in->abn", c, c, f)
+    expect = rho * (np.eye(3)[:, :, None] / 3 + u[:, None, :] * u[None, :, :])
+    assert np.allclose(P, expect)
+
+
+# ---------------------------------------------------------------- collision
+
+def test_collision_conserves_mass_and_adds_force():
+    """eq. (8): sum f* = rho and sum c f* = rho u_eq + F (EDM adds F dt)."""
+    n = 40
+    rho = RNG.uniform(0.3, 6.5, n)
+    ueq = RNG.uniform(-0.1, 0.1, (3, n))
+    F = RNG.uniform(-0.05, 0.05, (3, n))
+    f = O.feq19(rho, ueq) * (1 + RNG.uniform(-0.05, 0.05, (19, n)))
+    rho = f.sum(0)
+    ueq = (O.C19.T @ f) / rho
+    p = O.Params(n, 1, 1)
+    fs = O.collide19(f, rho, ueq, F / rho, p)
+    assert np.allclose(fs.sum(0), rho, rtol=1e-14)
+    assert np.allclose(O.C19.T @ fs, rho * ueq + F, rtol=1e-13, atol=1e-15)
+
+
+def test_uniform_rest_state_is_a_fixed_point():
+    """Uniform rho, T, u = 0 (so F = 0, div u = 0, grad T = 0): one full step
+    returns the same state (periodic box)."""
+    p = O.Params(6, 5, 4)
+    rho = np.full(p.shape, 0.3796789993997207)
+    T = np.full(p.shape, 0.86 * _tc())
+    f, g = O.init_populations(rho, T, p)
+    f2, g2, mac = O.step(f, g, p)
+    assert np.allclose(f2, f, rtol=1e-14, atol=1e-16)
+    assert np.allclose(g2, g, rtol=1e-14, atol=1e-16)
+    assert np.abs(mac["F"]).max() < 1e-15
+
+
+def test_stream19_brute_force_periodic():
+    """eq. (9) against an explicit loop over cells on a tiny periodic box."""
+    p = O.Params(3, 4, 2)
+    fs = RNG.uniform(size=(19,) + p.shape)
+    out = O.stream19(fs, p)
+    for i in range(19):
+        cx, cy, cz = O.C19[i]
+        for z in range(p.nz):
+            for y in range(p.ny):
+                for x in range(p.nx):
+                    d = ((z + cz) % p.nz, (y + cy) % p.ny, (x + cx) % p.nx)
+                    assert out[i][d] == fs[i, z, y, x]
+
+
+def test_bounce_back_brute_force():
+    """eq. (34) at a z = 0 wall: every slot fed from below equals the
+    post-collision value of the opposite link at the same node."""
+    p = O.Params(3, 3, 4, faces=(0, 0, 0, 0, O.WALL, O.WALL))
+    fs = RNG.uniform(size=(19,) + p.shape)
+    out = O.stream19(fs, p)
+    for i in range(19):
+        if O.C19[i, 2] == 1:
+            assert np.array_equal(out[i, 0], fs[O.OPP19[i], 0])
+        if O.C19[i, 2] == -1:
+            assert np.array_equal(out[i, -1], fs[O.OPP19[i], -1])
+    assert np.isfinite(out).all()
+
+
+# ---------------------------------------------------------------- stencils
+
+def _open_params(n=8):
+    return O.Params(n, n + 1, n + 2, faces=(O.PRESSURE,) * 6)
+
+
+@pytest.mark.parametrize("kind", ["linear", "quadratic"])
+def test_force_stencil_is_exact_gradient(kind):
+    """eq. (6) with varpi(1) = 1/6, varpi(2) = 1/12: sum varpi psi(x+c) c is
+    exactly grad psi for linear and quadratic psi, so F = -G psi grad psi."""
+    p = _open_params()
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=float) for n in p.shape), indexing="ij")
+    if kind == "linear":
+        psi = 1.0 + 0.1 * x - 0.05 * y + 0.02 * z
+        grad = np.stack([np.full(x.shape, 0.1), np.full(x.shape, -0.05), np.full(x.shape, 0.02)])
+    else:
+        psi = 1.0 + 0.01 * x * x + 0.02 * x * y - 0.03 * z * z + 0.01 * y * z
+        grad = np.stack([0.02 * x + 0.02 * y, 0.02 * x + 0.01 * z, -0.06 * z + 0.01 * y])
+    F = O.interaction_force(psi, p)
+    inner = (slice(None), slice(1, -1), slice(1, -1), slice(1, -1))
+    assert np.allclose(F[inner], (-p.G * psi * grad)[inner], rtol=1e-12, atol=1e-14)
+
+
+def test_divergence_stencil_is_exact():
+    """Isotropic divergence (Sec. 2.2): exact for quadratic velocity fields."""
+    p = _open_params()
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=float) for n in p.shape), indexing="ij")
+    u = np.stack([0.01 * x * x + 0.02 * y, 0.03 * x * y - 0.01 * z * z, 0.02 * z * x])
+    div = 0.02 * x + 0.03 * x + 0.02 * x
+    d = O.divergence(u, p)
+    assert np.allclose(d[1:-1, 1:-1, 1:-1], div[1:-1, 1:-1, 1:-1], rtol=1e-12, atol=1e-14)
+
+
+def test_force_sums_to_zero_on_periodic_box():
+    """eq. (6) is pairwise antisymmetric: sum_x F(x) = 0 on a periodic box."""
+    p = O.Params(7, 6, 5)
+    psi = RNG.uniform(0.5, 2.0, p.shape)
+    F = O.interaction_force(psi, p)
+    assert np.abs(F.sum(axis=(1, 2, 3))).max() < 1e-12
+
+
+def test_wetting_ghost_layer_brute_force():
+    """eq. (37) at a z = 0 wall with kappa = tan(pi/2 - theta)."""
+    p = O.Params(5, 4, 6, faces=(0, 0, 0, 0, O.WALL, O.WALL), kappa_w=0.37)
+    psi = RNG.uniform(0.5, 2.0, p.shape)
+    P = O.pad_psi(psi, p)
+    for y in range(p.ny):
+        for x in range(p.nx):
+            dx = psi[0, y, (x + 1) % p.nx] - psi[0, y, (x - 1) % p.nx]
+            dy = psi[0, (y + 1) % p.ny, x] - psi[0, (y - 1) % p.ny, x]
+            expect = psi[1, y, x] + np.sqrt(dx * dx + dy * dy) * 0.37
+            assert abs(P[0, y + 1, x + 1] - expect) < 1e-14
+            dx = psi[-1, y, (x + 1) % p.nx] - psi[-1, y, (x - 1) % p.nx]
+            dy = psi[-1, (y + 1) % p.ny, x] - psi[-1, (y - 1) % p.ny, x]
+            expect = psi[-2, y, x] + np.sqrt(dx * dx + dy * dy) * 0.37
+            assert abs(P[-1, y + 1, x + 1] - expect) < 1e-14
+
+
+# ---------------------------------------------------------------- boundaries
+
+def test_thermal_dirichlet_identity():
+    """eqs. (35)-(36): after the extrapolation sum_i g_i(x_b) = T_b exactly,
+    on faces, edges and corners, and with a wall-temperature field."""
+    p = O.Params(6, 5, 7, faces=(O.PRESSURE,) * 6, face_T=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6),
+                 face_rho=(0.4,) * 6)
+    g = RNG.uniform(0.01, 0.02, (7,) + p.shape)
+    g2 = O.thermal_dirichlet(g, p)
+    T = g2.sum(0)
+    _, count, _, prio = O._boundary_nodes(p)
+    Tb = np.array(p.face_T)[prio]
+    assert np.allclose(T[count > 0], Tb[count > 0], rtol=1e-14)
+    assert np.array_equal(g2[:, count == 0], g[:, count == 0])
+    # non-equilibrium part copied from the inward neighbour: face node example
+    w = O.w7(p.wbar)
+    neq_b = g2[:, 3, 2, 0] - w * g2[:, 3, 2, 0].sum()
+    neq_f = g[:, 3, 2, 1] - w * g[:, 3, 2, 1].sum()
+    assert np.allclose(neq_b, neq_f, atol=1e-16)
+    # wall field
+    pw = O.Params(4, 3, 5, faces=(0, 0, 0, 0, O.WALL, O.PRESSURE), face_T=(0, 0, 0, 0, 9, 0.2))
+    Tw = RNG.uniform(0.1, 0.2, (3, 4))
+    g = RNG.uniform(0.01, 0.02, (7,) + pw.shape)
+    T = O.thermal_dirichlet(g, pw, {4: Tw}).sum(0)
+    assert np.allclose(T[0], Tw, rtol=1e-14)
+    assert np.allclose(T[-1], 0.2, rtol=1e-14)
+
+
+def test_zou_he_plus_z_matches_printed_formulas():
+    """Sec. 3.3, eqs. (41), (42), (50)-(53) for the +z outlet, typed in as
+    printed, against the oracle's symmetry-mapped fill."""
+    m = 30
+    f = RNG.uniform(0.01, 0.05, (19, m))
+    F = RNG.uniform(-0.01, 0.01, (3, m))
+    rho = RNG.uniform(0.3, 0.5, m)
+    out = O.zou_he_face(f, F, rho, 5)
+    Fx, Fy, Fz = F
+    uz = (f[0] + f[1] + f[2] + f[3] + f[4] + f[7] + f[8] + f[9] + f[10]
+          + 2 * (f[5] + f[11] + f[14] + f[15] + f[18]) + 0.5 * Fz) / rho - 1
+    e = {
+        6: f[5] - rho * uz / 3,
+        12: f[11] + 0.5 * (f[1] - f[2]) + 0.5 * (f[7] - f[8]) + 0.5 * (f[9] - f[10])
+        + (2 * Fx + Fz) / 8 - rho * uz / 6,
+        13: f[14] - 0.5 * (f[1] - f[2]) - 0.5 * (f[7] - f[8]) - 0.5 * (f[9] - f[10])
+        - (2 * Fx - Fz) / 8 - rho * uz / 6,
+        16: f[15] + 0.5 * (f[3] - f[4]) + 0.5 * (f[7] - f[8]) - 0.5 * (f[9] - f[10])
+        + (2 * Fy + Fz) / 8 - rho * uz / 6,
+        17: f[18] - 0.5 * (f[3] - f[4]) - 0.5 * (f[7] - f[8]) + 0.5 * (f[9] - f[10])
+        - (2 * Fy - Fz) / 8 - rho * uz / 6,
+    }
+    for i, v in e.items():
+        assert np.allclose(out[i], v, rtol=1e-13, atol=1e-16), i
+    others = [i for i in range(19) if i not in e]
+    assert np.array_equal(out[others], f[others])
+
+
+@pytest.mark.parametrize("face", range(6))
+def test_zou_he_closure_every_face(face):
+    """Sec. 3.3 closure on every face: after the fill sum f = rho_out, the
+    tangential momenta plus F_t/2 vanish, and the normal momentum plus F_n/2
+    equals rho_out u_n with u_n from the known populations (eq. (41))."""
+    m = 25
+    f = RNG.uniform(0.01, 0.05, (19, m))
+    F = RNG.uniform(-0.01, 0.01, (3, m))
+    rho = RNG.uniform(0.3, 0.5, m)
+    out = O.zou_he_face(f, F, rho, face)
+    a = O.FACE_AXIS[face]
+    s = O.FACE_SIGN[face]
+    c = O.C19.astype(float)
+    cn = O.C19[:, a] * s
+    un = (f[cn == 0].sum(0) + 2 * f[cn == 1].sum(0) + 0.5 * s * F[a]) / rho - 1
+    assert np.allclose(out.sum(0), rho, rtol=1e-13)
+    for t in range(3):
+        mom = c[:, t] @ out + 0.5 * F[t]
+        if t == a:
+            assert np.allclose(s * mom, rho * un, rtol=1e-12, atol=1e-15)
+        else:
+            assert np.allclose(mom, 0, atol=1e-15)
+    # known populations untouched
+    assert np.array_equal(out[cn >= 0], f[cn >= 0])
+
+
+def test_zou_he_edges_nonequilibrium_extrapolation():
+    """Edge/corner pressure nodes: sum f = rho_out and sum c f = rho_out
+    u_eq(x_f) (the extrapolated non-equilibrium part carries no mass or
+    momentum beyond x_f's)."""
+    p = O.Params(5, 6, 7, faces=(O.PRESSURE,) * 6, face_rho=(0.38,) * 6)
+    rho = RNG.uniform(0.35, 0.45, p.shape)
+    u = RNG.uniform(-0.01, 0.01, (3,) + p.shape)
+    f = O.feq19(rho, u) * (1 + RNG.uniform(-0.01, 0.01, (19,) + p.shape))
+    F = np.zeros((3,) + p.shape)
+    out = O.zou_he(f, F, p)
+    for (z, y, x), (fz, fy, fx) in [((0, 0, 0), (1, 1, 1)), ((6, 5, 4), (5, 4, 3)),
+                                     ((3, 0, 0), (3, 1, 1)), ((0, 2, 4), (1, 2, 3))]:
+        ff = f[:, fz, fy, fx]
+        ueq = (O.C19.T @ ff) / ff.sum()
+        assert abs(out[:, z, y, x].sum() - 0.38) < 1e-14
+        assert np.allclose(O.C19.T @ out[:, z, y, x], 0.38 * ueq, atol=1e-15)
+
+
+# ---------------------------------------------------------------- invariants
+
+def _droplet(p, T_over=0.86, R0=3.5, W=5.0, noise=0.0):
+    rv, rl = 0.3796789993997207, 6.4989457632878835
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=float) for n in p.shape), indexing="ij")
+    d = np.sqrt((x - p.nx / 2) ** 2 + (y - p.ny / 2) ** 2 + (z - p.nz / 2) ** 2)
+    rho = 0.5 * (rl + rv) - 0.5 * (rl - rv) * np.tanh(2 * (d - R0) / W)
+    if noise:
+        rho = rho + noise * RNG.uniform(-1, 1, rho.shape)
+    return rho, np.full(p.shape, T_over * _tc())
+
+
+def test_periodic_box_conserves_mass_and_momentum():
+    """Periodic box: sum rho constant and sum_x sum_i c_i f_i constant
+    (collision adds F, and sum_x F = 0)."""
+    p = O.Params(12, 10, 11)
+    rho, T = _droplet(p, noise=1e-3)
+    f, g = O.init_populations(rho, T, p)
+    M0 = f.sum()
+    P0 = np.tensordot(O.C19.T.astype(float), f, axes=(1, 0)).sum(axis=(1, 2, 3))
+    for _ in range(15):
+        f, g, _ = O.step(f, g, p)
+    assert abs(f.sum() - M0) / M0 < 1e-13
+    P = np.tensordot(O.C19.T.astype(float), f, axes=(1, 0)).sum(axis=(1, 2, 3))
+    assert np.abs(P - P0).max() < 1e-11
+
+
+def test_closed_box_conserves_mass():
+    """No-slip walls on both z faces, periodic x, y: bounce-back keeps sum rho."""
+    p = O.Params(10, 9, 8, faces=(0, 0, 0, 0, O.WALL, O.WALL), face_T=(0, 0, 0, 0, 0.09, 0.1),
+                 kappa_w=0.3)
+    rho, T = _droplet(p)
+    f, g = O.init_populations(rho, T, p)
+    M0 = f.sum()
+    for _ in range(15):
+        f, g, _ = O.step(f, g, p)
+    assert abs(f.sum() - M0) / M0 < 1e-13
+
+
+def test_energy_identity_periodic():
+    """With rho c_v taken at the destination (eq. (13)), on a periodic box
+    sum_y rho(y,t) c_v [T(y,t+1) - T(y,t)] = -sum_x Fbar(x,t) exactly, since
+    sum_i (M^-1 v)_i = v_0 and sum_i w_i = 1."""
+    p = O.Params(11, 10, 9)
+    rho, T = _droplet(p, noise=1e-2)
+    f, g = O.init_populations(rho, T, p)
+    for _ in range(3):
+        f, g, _ = O.step(f, g, p)
+    f2, g2, mac = O.step(f, g, p)
+    lhs = np.sum(mac["rho"] * p.cv * (g2.sum(0) - mac["T"]))
+    rhs = -np.sum(mac["Fbar"])
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, np.abs(mac["Fbar"]).sum())
+    assert np.abs(mac["Fbar"]).max() > 1e-6          # the identity is not vacuous
+
+
+def test_centred_droplet_symmetry():
+    """No noise, centre at N/2 on a periodic N^3 box: fields stay invariant
+    under x -> N - x and under exchanging axes (the relaxation rates are
+    constant on permutation-closed moment groups)."""
+    n = 12
+    p = O.Params(n, n, n)
+    rho, T = _droplet(p, R0=3.0)
+    f, g = O.init_populations(rho, T, p)
+    for _ in range(8):
+        f, g, _ = O.step(f, g, p)
+    r, u, T = O.fields(f, g, p)
+    idx = (-np.arange(n)) % n
+    assert np.allclose(r, r[:, :, idx], rtol=1e-12)
+    assert np.allclose(T, T[:, :, idx], rtol=1e-12)
+    assert np.allclose(r, np.transpose(r, (0, 2, 1)), rtol=1e-12)
+    assert np.allclose(r, np.transpose(r, (2, 1, 0)), rtol=1e-12)
+    assert np.allclose(u[0], -u[0][:, :, idx], atol=1e-13)
+
+
+# ---------------------------------------------------------------- thermal lattice
+
+def _thermal_only(g, rho, p, steps):
+    for _ in range(steps):
+        T = g.sum(0)
+        gs = O.collide7(g, T, np.zeros_like(T), p)
+        g = O.stream7_blend(gs, g, rho, p)
+    return g
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_thermal_sine_decay_matches_fourier_eigenvalue(N):
+    """Thermal lattice alone (uniform rho, u = 0, Fbar = 0) on a periodic line:
+    a sin(2 pi x/N) temperature decays per step by the dominant eigenvalue of
+    A(k) = (1 - b) I + b diag(exp(-i k c_j)) K, b = 1/(rho c_v), with the local
+    collision K = I - M^-1 L M (I - w 1^T) (a spectral, not real-space, route)."""
+    p = O.Params(N, 1, 1)
+    rho = np.full(p.shape, 0.8)
+    x = np.arange(N, dtype=float)
+    T = 0.1 + 0.001 * np.sin(2 * np.pi * x / N)
+    g = O.geq7(np.broadcast_to(T, p.shape).copy(), p)
+    g = _thermal_only(g, rho, p, 200)
+    a0 = np.abs(np.fft.fft(g.sum(0)[0, 0])[1])
+    g = _thermal_only(g, rho, p, 1)
+    a1 = np.abs(np.fft.fft(g.sum(0)[0, 0])[1])
+    k = 2 * np.pi / N
+    w = O.w7(p.wbar)
+    Minv = np.linalg.inv(O.M7.astype(float))
+    K = np.eye(7) - Minv @ np.diag(p.lambda7()) @ O.M7 @ (np.eye(7) - np.outer(w, np.ones(7)))
+    D = np.diag(np.exp(-1j * k * O.C7[:, 0]))
+    beta = 1.0 / (0.8 * p.cv)
+    A = (1 - beta) * np.eye(7) + beta * D @ K
+    lam = np.max(np.abs(np.linalg.eigvals(A)))
+    assert abs(a1 / a0 - lam) < 1e-12
+    # Chapman-Enskog limit: 1 - lam -> lambda k^2 / (rho c_v) (Sec. 2.2, after eq. (33))
+    rate = p.lam * k * k / (0.8 * p.cv)
+    assert abs((1 - lam) - rate) / rate < (0.03 if N == 16 else 0.008)
+
+
+def test_thermal_steady_linear_profile_between_dirichlet_planes():
+    """Thermal lattice alone between two Dirichlet planes: the steady state is
+    the linear profile and the local gradient of eqs. (27)-(29) equals its slope."""
+    nz = 12
+    p = O.Params(1, 1, nz, faces=(0, 0, 0, 0, O.WALL, O.WALL), face_T=(0, 0, 0, 0, 0.1, 0.13))
+    rho = np.full(p.shape, 1.3)
+    g = O.geq7(np.full(p.shape, 0.1), p)
+    for _ in range(4000):
+        g = O.thermal_dirichlet(g, p)
+        T = g.sum(0)
+        gs = O.collide7(g, T, np.zeros_like(T), p)
+        g = O.stream7_blend(gs, g, rho, p)
+    g = O.thermal_dirichlet(g, p)
+    T = g.sum(0)[:, 0, 0]
+    slope = 0.03 / (nz - 1)
+    assert np.allclose(T, 0.1 + slope * np.arange(nz), rtol=1e-10)
+    mz = (O.C7[:, 2].astype(float) @ g.reshape(7, -1)).reshape(nz)
+    gradT = -p.varsigma_flux * mz / p.cs2_T
+    assert np.allclose(gradT[1:-1], slope, rtol=1e-8)
+
+
+# ---------------------------------------------------------------- EOS
+
+def test_pr_critical_point():
+    """eq. (55): at Tc the isotherm has an inflection with zero slope at the
+    critical density (up to the rounding of 0.45724 and 0.0778), and
+    p_c/(rho_c R Tc) is the Peng-Robinson critical compressibility 0.3074."""
+    from scipy.optimize import brentq
+    p = O.Params(1, 1, 1)
+    Tc = O.critical_temperature(p)
+    h = 1e-4
+
+    def d2(r):
+        return (O.pr_pressure(r + h, Tc, p) - 2 * O.pr_pressure(r, Tc, p)
+                + O.pr_pressure(r - h, Tc, p)) / h**2
+
+    rc = brentq(d2, 1.0, 5.0)
+    d1 = (O.pr_pressure(rc + 1e-6, Tc, p) - O.pr_pressure(rc - 1e-6, Tc, p)) / 2e-6
+    assert abs(d1) < 1e-4 * p.R * Tc
+    pc = 0.0778 * p.R * Tc / p.b
+    assert abs(O.pr_pressure(rc, Tc, p) - pc) / pc < 1e-3
+    assert abs(pc / (rc * p.R * Tc) - 0.3074) < 1e-3
+
+
+def test_pr_dpdT_against_finite_difference():
+    p = O.Params(1, 1, 1)
+    Tc = O.critical_temperature(p)
+    rho = np.linspace(0.1, 8.0, 50)
+    for T in (0.8 * Tc, 0.86 * Tc, 1.1 * Tc):
+        h = 1e-6 * T
+        fd = (O.pr_pressure(rho, T + h, p) - O.pr_pressure(rho, T - h, p)) / (2 * h)
+        assert np.allclose(O.pr_dp_dT(rho, T, p), fd, rtol=1e-7)
+
+
+def test_psi_real_over_working_range():
+    """eq. (7) with G = -1 needs rho/3 > p_EOS: true over the working range at
+    0.86 Tc (below ~8.97) and false close to the co-volume limit 1/b."""
+    p = O.Params(1, 1, 1)
+    T = 0.86 * O.critical_temperature(p)
+    assert (O.psi_radicand(np.linspace(1e-3, 8.9, 2000), T, p) > 0).all()
+    assert O.psi_radicand(9.2, T, p) < 0
+
+
+def test_maxwell_equal_area_and_pressures():
+    """Maxwell construction: equal pressures and equal areas, checked by an
+    independent Simpson quadrature; near Tc the gap closes as (Tc - T)^(1/2)."""
+    from scipy.integrate import simpson
+    p = O.Params(1, 1, 1)
+    Tc = O.critical_temperature(p)
+    for t in (0.8, 0.86, 0.95):
+        rv, rl, ps = O.maxwell_coexistence(t * Tc, p)
+        assert abs(O.pr_pressure(rv, t * Tc, p) - ps) < 1e-13
+        assert abs(O.pr_pressure(rl, t * Tc, p) - ps) < 1e-13
+        r = np.linspace(rv, rl, 400001)
+        area = simpson((O.pr_pressure(r, t * Tc, p) - ps) / r**2, x=r)
+        assert abs(area) < 1e-10
+    gaps = [np.subtract(*O.maxwell_coexistence(t * Tc, p)[1::-1]) for t in (0.990, 0.995)]
+    assert abs((gaps[0] / gaps[1]) ** 2 - 2.0) < 0.05
+
+
+def test_stored_coexistence_table_matches_oracle():
+    from workloads import synth
+    tab = synth.coexistence_table()
+    p = O.Params(1, 1, 1)
+    assert abs(tab["Tc"] - O.critical_temperature(p)) < 1e-15
+    for row in tab["rows"][::37]:
+        rv, rl, ps = O.maxwell_coexistence(row[0] * tab["Tc"], p)
+        assert abs(rv - row[1]) < 1e-10 and abs(rl - row[2]) < 1e-10
+
+
+def test_splitmix64_reference_vector():
+    """Published SplitMix64 outputs for seed 0."""
+    from workloads import synth
+    z = synth.splitmix64(0, 3)
+    assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
