@@ -1,0 +1,254 @@
+// Per-cell lattice arithmetic of the coupled D3Q19 / D3Q7 step, shared by
+// every kernel of the library.  Method: Huang, Wang, He & Huang, arXiv
+// 2206.00946 (Sec. 2, Appendix A).  All populations handled here are
+// deviations from the rest equilibrium: ft_i = f_i - w_i rho_ref and
+// gt_i = g_i - w_i T_ref (rho_ref = T_ref = 0 gives the plain populations).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum { FACE_PERIODIC = 0, FACE_WALL = 1, FACE_PRESSURE = 2 };
+
+// D3Q19 velocities in the order fixed by rows 1-3 of the transform (A.1):
+// rest, +x, -x, +y, -y, +z, -z, then the xy, xz and yz face diagonals.
+constexpr int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+// opposite velocity: pairs (1,2), (3,4), ..., (17,18)
+__host__ __device__ constexpr int opp19(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// D3Q7: rest, +x, -x, +y, -y, +z, -z (rows 1-3 of (A.2)); the first seven D3Q19 ones.
+
+template <typename C>
+__host__ __device__ constexpr C w19(int i) {
+  return i == 0 ? C(1) / C(3) : (i < 7 ? C(1) / C(18) : C(1) / C(36));
+}
+
+// Physical and lattice parameters in the compute precision C.
+template <typename C>
+struct Phys {
+  C a, b, R, G, Tc, kpr;      // Peng-Robinson, eqs. (54)-(55); kpr = 0.37464 + 1.54226 w - 0.26992 w^2
+  C s_e, s_nu, s_q, s_pi;     // eq. (11)
+  C w0, w1, wbar, cs2T;       // D3Q7 weights and c_s^2 = wbar/3
+  C vflux, vother;            // varsigma_{1,2,3} and the remaining rates
+  C cv;
+  C kappa_w;                  // eq. (37)
+  C rho_ref, T_ref;           // deviation references
+  C inv_b;
+};
+
+// ---------------------------------------------------------------- EOS
+template <typename C>
+__device__ __forceinline__ C pr_xi_sq_root(C T, const Phys<C>& ph) {
+  // 1 + kappa (1 - sqrt(T/Tc)), whose square is xi(T)
+  return C(1) + ph.kpr * (C(1) - sqrt(T / ph.Tc));
+}
+
+template <typename C>
+__device__ __forceinline__ C pr_pressure(C rho, C T, const Phys<C>& ph) {
+  const C s = pr_xi_sq_root(T, ph);
+  const C br = ph.b * rho;
+  return rho * ph.R * T / (C(1) - br) - ph.a * (s * s) * rho * rho / (C(1) + C(2) * br - br * br);
+}
+
+// (d p / d T) at constant rho
+template <typename C>
+__device__ __forceinline__ C pr_dpdT(C rho, C T, const Phys<C>& ph) {
+  const C s = pr_xi_sq_root(T, ph);
+  const C dxi = -ph.kpr * s / sqrt(T * ph.Tc);
+  const C br = ph.b * rho;
+  return rho * ph.R / (C(1) - br) - ph.a * dxi * rho * rho / (C(1) + C(2) * br - br * br);
+}
+
+// radicand of eq. (7): 2 (p - rho c_s^2) / G with c_s^2 = 1/3
+template <typename C>
+__device__ __forceinline__ C psi_radicand(C rho, C T, const Phys<C>& ph) {
+  return C(2) * (pr_pressure(rho, T, ph) - rho / C(3)) / ph.G;
+}
+
+template <typename C>
+__device__ __forceinline__ bool nonphysical(C rho, C T, C rad, const Phys<C>& ph) {
+  // written so that NaN in any input also trips the flag
+  return !(rho > C(0)) || !(rho * ph.b < C(1)) || !(T > C(0)) || !(rad >= C(0));
+}
+
+// ---------------------------------------------------------------- D3Q19
+// Deviation moments m = M ft of the transform (A.1), written out row by row
+// (monomials 1, x, y, z, |c|^2, 2x^2-y^2-z^2, y^2-z^2, xy, xz, yz, x^2y, xy^2,
+// x^2z, xz^2, y^2z, yz^2, x^2y^2, x^2z^2, y^2z^2).
+template <typename C>
+__device__ __forceinline__ void moments19(const C* f, C* m) {
+  const C ax = f[1] + f[2], ay = f[3] + f[4], az = f[5] + f[6];
+  const C dxy = f[7] + f[8] + f[9] + f[10];
+  const C dxz = f[11] + f[12] + f[13] + f[14];
+  const C dyz = f[15] + f[16] + f[17] + f[18];
+  m[0] = f[0] + ax + ay + az + dxy + dxz + dyz;
+  const C a78 = f[7] - f[8], a910 = f[9] - f[10];
+  const C a1112 = f[11] - f[12], a1314 = f[13] - f[14];
+  const C a1516 = f[15] - f[16], a1718 = f[17] - f[18];
+  m[1] = (f[1] - f[2]) + a78 + a910 + a1112 + a1314;
+  m[2] = (f[3] - f[4]) + a78 - a910 + a1516 + a1718;
+  m[3] = (f[5] - f[6]) + a1112 - a1314 + a1516 - a1718;
+  m[4] = ax + ay + az + C(2) * (dxy + dxz + dyz);
+  m[5] = C(2) * ax - ay - az + dxy + dxz - C(2) * dyz;
+  m[6] = ay - az + dxy - dxz;
+  m[7] = (f[7] + f[8]) - (f[9] + f[10]);
+  m[8] = (f[11] + f[12]) - (f[13] + f[14]);
+  m[9] = (f[15] + f[16]) - (f[17] + f[18]);
+  m[10] = a78 - a910;
+  m[11] = a78 + a910;
+  m[12] = a1112 - a1314;
+  m[13] = a1112 + a1314;
+  m[14] = a1516 - a1718;
+  m[15] = a1516 + a1718;
+  m[16] = dxy;
+  m[17] = dxz;
+  m[18] = dyz;
+}
+
+// Inverse transform f = M^-1 m, solved group by group: each face-diagonal
+// quadruple from its four moments, the axis pairs from the second-order
+// moments, the rest population from m0 and m4.
+template <typename C>
+__device__ __forceinline__ void populations19(const C* m, C* f) {
+  const C q = C(0.25);
+  f[7] = q * (m[16] + m[10] + m[11] + m[7]);
+  f[8] = q * (m[16] - m[10] - m[11] + m[7]);
+  f[9] = q * (m[16] - m[10] + m[11] - m[7]);
+  f[10] = q * (m[16] + m[10] - m[11] - m[7]);
+  f[11] = q * (m[17] + m[12] + m[13] + m[8]);
+  f[12] = q * (m[17] - m[12] - m[13] + m[8]);
+  f[13] = q * (m[17] - m[12] + m[13] - m[8]);
+  f[14] = q * (m[17] + m[12] - m[13] - m[8]);
+  f[15] = q * (m[18] + m[14] + m[15] + m[9]);
+  f[16] = q * (m[18] - m[14] - m[15] + m[9]);
+  f[17] = q * (m[18] - m[14] + m[15] - m[9]);
+  f[18] = q * (m[18] + m[14] - m[15] - m[9]);
+  const C S = m[4] - C(2) * (m[16] + m[17] + m[18]);      // sum of the six axis populations
+  const C P = m[5] - m[16] - m[17] + C(2) * m[18];         // 2A - B - C
+  const C Q = m[6] - m[16] + m[17];                         // B - C
+  const C A = (S + P) / C(3);
+  const C B = C(0.5) * (S - A + Q);
+  const C Cz = C(0.5) * (S - A - Q);
+  const C dx = m[1] - m[11] - m[13];
+  const C dy = m[2] - m[10] - m[15];
+  const C dz = m[3] - m[12] - m[14];
+  f[0] = m[0] - m[4] + m[16] + m[17] + m[18];
+  f[1] = C(0.5) * (A + dx);
+  f[2] = C(0.5) * (A - dx);
+  f[3] = C(0.5) * (B + dy);
+  f[4] = C(0.5) * (B - dy);
+  f[5] = C(0.5) * (Cz + dz);
+  f[6] = C(0.5) * (Cz - dz);
+}
+
+// Velocity part q(rho, u) of the equilibrium moments of eq. (10): the
+// equilibrium moments are rho*e + q with e = moments of the rest weights
+// (1 at rows 0 and 4, 1/9 at rows 16-18, 0 elsewhere).
+template <typename C>
+__device__ __forceinline__ void meq_velocity_part(C rho, C ux, C uy, C uz, C* q) {
+  const C xx = ux * ux, yy = uy * uy, zz = uz * uz;
+  const C usq = xx + yy + zz;
+  const C third = C(1) / C(3);
+  const C r3 = rho * third;
+  q[0] = C(0);
+  q[1] = rho * ux;
+  q[2] = rho * uy;
+  q[3] = rho * uz;
+  q[4] = rho * usq;
+  q[5] = rho * (C(2) * xx - yy - zz);
+  q[6] = rho * (yy - zz);
+  q[7] = rho * ux * uy;
+  q[8] = rho * ux * uz;
+  q[9] = rho * uy * uz;
+  q[10] = r3 * uy;
+  q[11] = r3 * ux;
+  q[12] = r3 * uz;
+  q[13] = r3 * ux;
+  q[14] = r3 * uz;
+  q[15] = r3 * uy;
+  const C rest = -rho * usq / C(6);
+  q[16] = rest + r3 * (xx + yy);
+  q[17] = rest + r3 * (xx + zz);
+  q[18] = rest + r3 * (yy + zz);
+}
+
+template <typename C>
+__device__ __forceinline__ C rest_moment(int k) {
+  return (k == 0 || k == 4) ? C(1) : (k >= 16 ? C(1) / C(9) : C(0));
+}
+
+template <typename C>
+__device__ __forceinline__ C rate19(int k, const Phys<C>& ph) {
+  return k < 4 ? C(1) : (k == 4 ? ph.s_e : (k < 10 ? ph.s_nu : (k < 16 ? ph.s_q : ph.s_pi)));
+}
+
+// eq. (8): m* = m - L (m - meq(u_eq)) + [meq(u_eq + du) - meq(u_eq)], applied
+// to deviations: mt*_k = (1 - s_k)(mt_k - rt e_k - q_k(u_eq)) + rt e_k + q_k(u_eq + du),
+// rt = rho - rho_ref.  f is overwritten by the post-collision deviations.
+template <typename C>
+__device__ __forceinline__ void collide19(C* f, C rho, C rt, C ux, C uy, C uz, C dux, C duy,
+                                          C duz, const Phys<C>& ph) {
+  C m[19], q0[19], q1[19];
+  moments19(f, m);
+  meq_velocity_part(rho, ux, uy, uz, q0);
+  meq_velocity_part(rho, ux + dux, uy + duy, uz + duz, q1);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const C e = rt * rest_moment<C>(k);
+    m[k] = (C(1) - rate19(k, ph)) * (m[k] - e - q0[k]) + e + q1[k];
+  }
+  populations19(m, f);
+}
+
+// ---------------------------------------------------------------- D3Q7
+// Collision of eq. (13) with the D3Q7 transform (A.2) and theta = 0, on
+// deviations: n = M gt, n* = n - L (n - (Tt, 0, 0, 0, wbar Tt, 0, 0)),
+// gt* = M^-1 n* - w_i Fbar (source of eq. (15)).  Tt = T - T_ref = n0.
+template <typename C>
+__device__ __forceinline__ void collide7(C* g, C Fbar, const Phys<C>& ph) {
+  const C n0 = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6];
+  C n1 = g[1] - g[2], n2 = g[3] - g[4], n3 = g[5] - g[6];
+  C n4 = g[1] + g[2] + g[3] + g[4] + g[5] + g[6];
+  C n5 = g[1] + g[2] - g[3] - g[4];
+  C n6 = g[1] + g[2] - g[5] - g[6];
+  const C om = C(1) - ph.vother;
+  const C of = C(1) - ph.vflux;
+  n1 *= of;
+  n2 *= of;
+  n3 *= of;
+  n4 = n4 - ph.vother * (n4 - ph.wbar * n0);
+  n5 *= om;
+  n6 *= om;
+  const C s6 = n4 / C(6);
+  const C a = (n5 + n6) / C(6);
+  g[0] = n0 - n4 - ph.w0 * Fbar;
+  g[1] = C(0.5) * n1 + s6 + a - ph.w1 * Fbar;
+  g[2] = -C(0.5) * n1 + s6 + a - ph.w1 * Fbar;
+  g[3] = C(0.5) * n2 + s6 - n5 / C(3) + n6 / C(6) - ph.w1 * Fbar;
+  g[4] = -C(0.5) * n2 + s6 - n5 / C(3) + n6 / C(6) - ph.w1 * Fbar;
+  g[5] = C(0.5) * n3 + s6 + n5 / C(6) - n6 / C(3) - ph.w1 * Fbar;
+  g[6] = -C(0.5) * n3 + s6 + n5 / C(6) - n6 / C(3) - ph.w1 * Fbar;
+}
+
+// eqs. (27)-(29): c_s^2 dT/dx_a = -varsigma_a m_a (dt = 1) with the
+// pre-collision first moments of g (their equilibrium part is zero).
+template <typename C>
+__device__ __forceinline__ void local_gradT(const C* g, const Phys<C>& ph, C& gx, C& gy, C& gz) {
+  const C k = -ph.vflux / ph.cs2T;
+  gx = k * (g[1] - g[2]);
+  gy = k * (g[3] - g[4]);
+  gz = k * (g[5] - g[6]);
+}
+
+// eq. (2) deviation: f^eq_i(rho, u) - w_i rho_ref
+template <typename C>
+__device__ __forceinline__ C feq19_dev(int i, C rho, C rho_ref, C ux, C uy, C uz) {
+  const C cu = C(CX[i]) * ux + C(CY[i]) * uy + C(CZ[i]) * uz;
+  const C usq = ux * ux + uy * uy + uz * uz;
+  return w19<C>(i) * (rho * (C(1) + C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq) - rho_ref);
+}
+
+}  // namespace lbm

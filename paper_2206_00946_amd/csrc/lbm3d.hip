@@ -1,0 +1,540 @@
+// C ABI of the coupled D3Q19 / D3Q7 thermal pseudopotential LBM library for
+// MI355X (gfx950).  See include/lbm3d.h for the contract of every entry point.
+#include "lbm3d.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels_ref.h"
+#include "kernels_fused.h"
+
+using namespace lbm;
+
+namespace {
+
+std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+constexpr long long kSlab = 1ll << 22;  // cells per host<->device staging slab
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t elem_size(int prec) {
+  switch (prec) {
+    case LBM_FP64: return 8;
+    case LBM_FP32_DEV: return 4;
+    default: return 2;
+  }
+}
+size_t compute_size(int prec) { return prec == LBM_FP64 ? 8 : 4; }
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  hipStream_t stream = nullptr;
+  char* base = nullptr;
+  size_t bytes = 0;
+  bool owns = false;
+  // populations (A = current state, B = next)
+  void* fA = nullptr;
+  void* gA = nullptr;
+  void* fB = nullptr;
+  void* gB = nullptr;
+  // fields in the compute precision
+  void* rho = nullptr;
+  void* T = nullptr;
+  void* psi = nullptr;
+  void* ueq = nullptr;
+  void* du = nullptr;
+  double* Tw[2] = {nullptr, nullptr};
+  bool has_Tw[2] = {false, false};
+  double* partials = nullptr;
+  double* sums = nullptr;
+  int* flag = nullptr;
+  double* staging = nullptr;  // kSlab * 26 doubles
+  bool initialised = false;
+  int64_t step = 0;
+  double mass0 = 0.0;
+  bool fused_ok = false;
+  std::string err;
+};
+
+namespace {
+
+long long ncells(const lbm_params& p) { return (long long)p.nx * p.ny * p.nz; }
+
+struct Layout {
+  size_t state = 0, scratch = 0;
+  size_t off_fA, off_gA, off_fB, off_gB, off_rho, off_T, off_psi, off_ueq, off_du, off_Tw0, off_Tw1, off_part,
+      off_sums, off_flag, off_stage;
+};
+
+Layout layout_of(const lbm_params& p) {
+  Layout L;
+  const size_t N = (size_t)ncells(p);
+  const size_t es = elem_size(p.precision), cs = compute_size(p.precision);
+  size_t o = 0;
+  L.off_fA = o; o = align_up(o + 19 * N * es);
+  L.off_gA = o; o = align_up(o + 7 * N * es);
+  L.off_fB = o; o = align_up(o + 19 * N * es);
+  L.off_gB = o; o = align_up(o + 7 * N * es);
+  L.state = o;
+  L.off_rho = o; o = align_up(o + N * cs);
+  L.off_T = o; o = align_up(o + N * cs);
+  L.off_psi = o; o = align_up(o + N * cs);
+  L.off_ueq = o; o = align_up(o + 3 * N * cs);
+  L.off_du = o; o = align_up(o + 3 * N * cs);
+  L.off_Tw0 = o; o = align_up(o + (size_t)p.nx * p.ny * 8);
+  L.off_Tw1 = o; o = align_up(o + (size_t)p.nx * p.ny * 8);
+  L.off_part = o; o = align_up(o + RED_BLOCKS * RED_VALUES * 8);
+  L.off_sums = o; o = align_up(o + RED_VALUES * 8);
+  L.off_flag = o; o = align_up(o + 64);
+  L.off_stage = o; o = align_up(o + (size_t)std::min<long long>(kSlab, (long long)N) * 26 * 8);
+  L.scratch = o - L.state;
+  return L;
+}
+
+bool in_open01(double v) { return v > 0.0 && v < 1.0; }
+bool in_rate(double v) { return v > 0.0 && v < 2.0; }
+
+lbm_status validate(const lbm_params* p, std::string& msg) {
+  if (!p) { msg = "params is NULL"; return LBM_EINVAL; }
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) { msg = "grid sizes must be positive"; return LBM_EINVAL; }
+  if ((double)p->nx * p->ny * p->nz > 4.0e9) { msg = "grid too large"; return LBM_EINVAL; }
+  if (p->precision < LBM_FP64 || p->precision > LBM_BF16_DEV) { msg = "unknown precision"; return LBM_EINVAL; }
+  for (int k = 0; k < 6; ++k)
+    if (p->face[k] < LBM_FACE_PERIODIC || p->face[k] > LBM_FACE_PRESSURE) { msg = "unknown face kind"; return LBM_EINVAL; }
+  const int ext[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a) {
+    const bool lo = p->face[2 * a] == LBM_FACE_PERIODIC, hi = p->face[2 * a + 1] == LBM_FACE_PERIODIC;
+    if (lo != hi) { msg = "periodic faces must come in pairs"; return LBM_EINVAL; }
+    if (!lo && ext[a] < 3) { msg = "a bounded axis needs at least 3 cells"; return LBM_EINVAL; }
+  }
+  if (!(p->a > 0 && p->b > 0 && p->R > 0 && p->omega > -1 && std::isfinite(p->G) && p->G != 0.0)) {
+    msg = "invalid equation-of-state parameters"; return LBM_EINVAL;
+  }
+  if (!(in_rate(p->s_e) && in_rate(p->s_nu) && in_rate(p->s_q) && in_rate(p->s_pi) && in_rate(p->s_T_other))) {
+    msg = "relaxation rates must lie in (0, 2)"; return LBM_EINVAL;
+  }
+  if (!in_open01(p->wbar)) { msg = "wbar must lie in (0, 1)"; return LBM_EINVAL; }
+  if (!(p->lambda > 0 && p->cv > 0)) { msg = "lambda and cv must be positive"; return LBM_EINVAL; }
+  if (!(std::isfinite(p->kappa_w) && std::isfinite(p->rho_ref) && std::isfinite(p->T_ref))) {
+    msg = "kappa_w, rho_ref and T_ref must be finite"; return LBM_EINVAL;
+  }
+  for (int k = 0; k < 6; ++k) {
+    if (p->face[k] != LBM_FACE_PERIODIC && !(p->face_T[k] > 0)) { msg = "bounded faces need face_T > 0"; return LBM_EINVAL; }
+    if (p->face[k] == LBM_FACE_PRESSURE && !(p->face_rho[k] > 0 && p->face_rho[k] * p->b < 1)) {
+      msg = "pressure faces need 0 < face_rho < 1/b"; return LBM_EINVAL;
+    }
+  }
+  if (p->theta_corr != 0) { msg = "the correction term S_i (theta = 1) is not implemented"; return LBM_EUNSUPPORTED; }
+  for (int k = 0; k < 4; ++k)
+    if (p->face[k] == LBM_FACE_WALL) { msg = "walls are supported on the z faces only"; return LBM_EUNSUPPORTED; }
+  if ((p->face[4] == LBM_FACE_WALL || p->face[5] == LBM_FACE_WALL))
+    for (int k = 0; k < 4; ++k)
+      if (p->face[k] != LBM_FACE_PERIODIC) { msg = "a z wall requires periodic x and y"; return LBM_EUNSUPPORTED; }
+  return LBM_OK;
+}
+
+template <typename C>
+Phys<C> phys_of(const lbm_params& p) {
+  Phys<C> ph;
+  const double Tc = 0.0778 * p.a / (0.45724 * p.b * p.R);  // eq. (55) solved for Tc
+  const double kpr = 0.37464 + 1.54226 * p.omega - 0.26992 * p.omega * p.omega;
+  const double cs2T = p.wbar / 3.0;
+  ph.a = (C)p.a; ph.b = (C)p.b; ph.R = (C)p.R; ph.G = (C)p.G; ph.Tc = (C)Tc; ph.kpr = (C)kpr;
+  ph.s_e = (C)p.s_e; ph.s_nu = (C)p.s_nu; ph.s_q = (C)p.s_q; ph.s_pi = (C)p.s_pi;
+  ph.w0 = (C)(1.0 - p.wbar); ph.w1 = (C)(p.wbar / 6.0); ph.wbar = (C)p.wbar; ph.cs2T = (C)cs2T;
+  ph.vflux = (C)(1.0 / (0.5 + p.lambda / cs2T));  // lambda = (1/varsigma - 1/2) c_s^2
+  ph.vother = (C)p.s_T_other;
+  ph.cv = (C)p.cv;
+  ph.kappa_w = (C)p.kappa_w;
+  ph.rho_ref = (C)p.rho_ref;
+  ph.T_ref = (C)p.T_ref;
+  ph.inv_b = (C)(1.0 / p.b);
+  return ph;
+}
+
+Geom geom_of(const lbm_params& p) {
+  Geom g;
+  g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+  for (int k = 0; k < 6; ++k) g.face[k] = p.face[k];
+  g.N = ncells(p);
+  return g;
+}
+
+template <typename C>
+Faces<C> faces_of(const lbm_ctx* ctx) {
+  Faces<C> fc;
+  for (int k = 0; k < 6; ++k) {
+    fc.face_T[k] = (C)ctx->p.face_T[k];
+    fc.face_rho[k] = (C)ctx->p.face_rho[k];
+  }
+  fc.Tw[0] = ctx->has_Tw[0] ? ctx->Tw[0] : nullptr;
+  fc.Tw[1] = ctx->has_Tw[1] ? ctx->Tw[1] : nullptr;
+  return fc;
+}
+
+lbm_status hip_fail(lbm_ctx* ctx, hipError_t e, const char* where) {
+  ctx->err = std::string(where) + ": " + hipGetErrorString(e);
+  return LBM_EHIP;
+}
+
+#define HIPCHK(ctx, call)                                   \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);  \
+  } while (0)
+
+unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// ------------------------------------------------------------- dispatch by storage type
+
+template <typename S>
+struct Impl {
+  using C = typename Storage<S>::C;
+
+  static hipError_t thermal_dirichlet(lbm_ctx* ctx, S* g) {
+    const lbm_params& p = ctx->p;
+    const Geom geo = geom_of(p);
+    const long long plane = std::max({(long long)p.nx * p.ny, (long long)p.nx * p.nz, (long long)p.ny * p.nz});
+    dim3 grid(blocks_for(plane), 6);
+    hipLaunchKernelGGL(k_thermal_dirichlet<S>, grid, dim3(256), 0, ctx->stream, g, geo, faces_of<C>(ctx),
+                       phys_of<C>(p));
+    return hipGetLastError();
+  }
+
+  // S0-S5 on the state A: complete boundary nodes, fill rho, T, psi, u_eq, du.
+  static hipError_t prepass(lbm_ctx* ctx) {
+    const lbm_params& p = ctx->p;
+    const Geom geo = geom_of(p);
+    const Phys<C> ph = phys_of<C>(p);
+    const Faces<C> fc = faces_of<C>(ctx);
+    const unsigned nb = blocks_for(geo.N);
+    S* fA = (S*)ctx->fA;
+    S* gA = (S*)ctx->gA;
+    hipError_t e = thermal_dirichlet(ctx, gA);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_macro<S>, dim3(nb), dim3(256), 0, ctx->stream, fA, gA, (C*)ctx->rho, (C*)ctx->T,
+                       (C*)ctx->psi, ctx->flag, geo, fc, ph);
+    hipLaunchKernelGGL(k_force<S>, dim3(nb), dim3(256), 0, ctx->stream, fA, (const C*)ctx->rho,
+                       (const C*)ctx->psi, (C*)ctx->ueq, (C*)ctx->du, geo, fc, ph);
+    return hipGetLastError();
+  }
+
+  static hipError_t step_ref(lbm_ctx* ctx) {
+    hipError_t e = prepass(ctx);
+    if (e != hipSuccess) return e;
+    const Geom geo = geom_of(ctx->p);
+    hipLaunchKernelGGL(k_collide_push<S>, dim3(blocks_for(geo.N)), dim3(256), 0, ctx->stream, (const S*)ctx->fA,
+                       (const S*)ctx->gA, (S*)ctx->fB, (S*)ctx->gB, (const C*)ctx->rho, (const C*)ctx->T,
+                       (const C*)ctx->ueq, (const C*)ctx->du, geo, phys_of<C>(ctx->p));
+    return hipGetLastError();
+  }
+
+  static hipError_t step(lbm_ctx* ctx) {
+    hipError_t e = ctx->fused_ok ? FusedImpl<S>::step(ctx->p, ctx->stream, (const S*)ctx->fA, (const S*)ctx->gA,
+                                                      (S*)ctx->fB, (S*)ctx->gB, ctx->Tw[0], ctx->has_Tw[0],
+                                                      ctx->Tw[1], ctx->has_Tw[1], ctx->flag)
+                                 : step_ref(ctx);
+    if (e != hipSuccess) return e;
+    std::swap(ctx->fA, ctx->fB);
+    std::swap(ctx->gA, ctx->gB);
+    return hipSuccess;
+  }
+
+  static hipError_t init_slab(lbm_ctx* ctx, const double* drho, const double* du, const double* dT, long long c0,
+                              long long len) {
+    const lbm_params& p = ctx->p;
+    hipLaunchKernelGGL(k_init<S>, dim3(blocks_for(len)), dim3(256), 0, ctx->stream, (S*)ctx->fA, (S*)ctx->gA, drho,
+                       du, dT, c0, len, ncells(p), p.rho_ref, p.T_ref, 1.0 - p.wbar, p.wbar / 6.0);
+    return hipGetLastError();
+  }
+
+  static hipError_t fields_slab(lbm_ctx* ctx, double* orho, double* ou, double* oT, long long c0, long long len,
+                                long long ustride) {
+    hipLaunchKernelGGL(k_fields_out<C>, dim3(blocks_for(len)), dim3(256), 0, ctx->stream, (const C*)ctx->rho,
+                       (const C*)ctx->T, (const C*)ctx->ueq, (const C*)ctx->du, orho, ou, oT, c0, len,
+                       ncells(ctx->p), ustride);
+    return hipGetLastError();
+  }
+
+  static hipError_t pops_slab(lbm_ctx* ctx, double* of, double* og, long long c0, long long len) {
+    const lbm_params& p = ctx->p;
+    hipLaunchKernelGGL(k_pops_out<S>, dim3(blocks_for(len)), dim3(256), 0, ctx->stream, (const S*)ctx->fA,
+                       (const S*)ctx->gA, of, og, c0, len, ncells(p), p.rho_ref, p.T_ref, 1.0 - p.wbar,
+                       p.wbar / 6.0);
+    return hipGetLastError();
+  }
+
+  static hipError_t diag(lbm_ctx* ctx) {
+    const lbm_params& p = ctx->p;
+    hipLaunchKernelGGL(k_diag_partials<C>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, ctx->stream, (const C*)ctx->rho,
+                       (const C*)ctx->T, ncells(p), p.cv, p.diag_rho_v, p.diag_rho_l, ctx->partials);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(RED_THREADS), 0, ctx->stream, (const double*)ctx->partials,
+                       RED_BLOCKS, ctx->sums);
+    return hipGetLastError();
+  }
+};
+
+template <typename F>
+hipError_t dispatch(lbm_ctx* ctx, F&& fn) {
+  switch (ctx->p.precision) {
+    case LBM_FP64: return fn(Impl<double>());
+    case LBM_FP32_DEV: return fn(Impl<float>());
+    case LBM_FP16_DEV: return fn(Impl<_Float16>());
+    default: return fn(Impl<bf16>());
+  }
+}
+
+lbm_status reduce_now(lbm_ctx* ctx, double out[RED_VALUES]) {
+  HIPCHK(ctx, dispatch(ctx, [&](auto impl) { return decltype(impl)::prepass(ctx); }));
+  HIPCHK(ctx, dispatch(ctx, [&](auto impl) { return decltype(impl)::diag(ctx); }));
+  HIPCHK(ctx, hipMemcpyAsync(out, ctx->sums, RED_VALUES * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_default_params(lbm_params* p, int32_t nx, int32_t ny, int32_t nz) {
+  if (!p) return LBM_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = nx; p->ny = ny; p->nz = nz;
+  p->precision = LBM_FP32_DEV;
+  p->a = 3.0 / 49.0; p->b = 2.0 / 21.0; p->R = 1.0; p->omega = 0.344; p->G = -1.0;
+  p->s_e = 1.25; p->s_nu = 0.8; p->s_q = 1.0; p->s_pi = 1.0;
+  p->wbar = 0.75; p->lambda = 1.0 / 3.0; p->cv = 5.0; p->s_T_other = 1.0;
+  p->theta_corr = 0;
+  for (int k = 0; k < 6; ++k) { p->face[k] = LBM_FACE_PERIODIC; p->face_T[k] = 0.0; p->face_rho[k] = 0.0; }
+  p->kappa_w = 0.0;
+  const double Tc = 0.0778 * p->a / (0.45724 * p->b * p->R);
+  p->rho_ref = 0.3796789993997207;
+  p->T_ref = 0.86 * Tc;
+  p->diag_rho_v = 0.3796789993997207;
+  p->diag_rho_l = 6.4989457632878835;
+  return LBM_OK;
+}
+
+lbm_status lbm_required_bytes(const lbm_params* p, size_t* state_bytes, size_t* scratch_bytes) {
+  std::string msg;
+  const lbm_status s = validate(p, msg);
+  if (s != LBM_OK) { g_create_error = msg; return s; }
+  if (!state_bytes || !scratch_bytes) return LBM_EINVAL;
+  const Layout L = layout_of(*p);
+  *state_bytes = L.state;
+  *scratch_bytes = L.scratch;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_bytes, void* hip_stream,
+                      lbm_ctx** out) {
+  if (!out) { g_create_error = "out is NULL"; return LBM_EINVAL; }
+  *out = nullptr;
+  std::string msg;
+  const lbm_status s = validate(p, msg);
+  if (s != LBM_OK) { g_create_error = msg; return s; }
+  const Layout L = layout_of(*p);
+  const size_t need = L.state + L.scratch;
+  lbm_ctx* ctx = new (std::nothrow) lbm_ctx();
+  if (!ctx) { g_create_error = "host allocation failed"; return LBM_ENOMEM; }
+  ctx->p = *p;
+  ctx->stream = (hipStream_t)hip_stream;
+  if (device_buffer) {
+    if (buffer_bytes < need || ((uintptr_t)device_buffer % kAlign) != 0) {
+      g_create_error = "device_buffer too small or not 256-byte aligned";
+      delete ctx;
+      return LBM_ENOMEM;
+    }
+    ctx->base = (char*)device_buffer;
+    ctx->owns = false;
+  } else {
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, need);
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+      delete ctx;
+      return LBM_ENOMEM;
+    }
+    ctx->base = (char*)ptr;
+    ctx->owns = true;
+  }
+  ctx->bytes = need;
+  char* b = ctx->base;
+  ctx->fA = b + L.off_fA; ctx->gA = b + L.off_gA; ctx->fB = b + L.off_fB; ctx->gB = b + L.off_gB;
+  ctx->rho = b + L.off_rho; ctx->T = b + L.off_T; ctx->psi = b + L.off_psi;
+  ctx->ueq = b + L.off_ueq; ctx->du = b + L.off_du;
+  ctx->Tw[0] = (double*)(b + L.off_Tw0); ctx->Tw[1] = (double*)(b + L.off_Tw1);
+  ctx->partials = (double*)(b + L.off_part);
+  ctx->sums = (double*)(b + L.off_sums);
+  ctx->flag = (int*)(b + L.off_flag);
+  ctx->staging = (double*)(b + L.off_stage);
+  ctx->fused_ok = fused_supported(*p);
+  hipError_t e = hipMemsetAsync(ctx->flag, 0, 64, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
+    if (ctx->owns) (void)hipFree(ctx->base);
+    delete ctx;
+    return LBM_EHIP;
+  }
+  *out = ctx;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx* ctx, const double* rho, const double* u, const double* T) {
+  if (!ctx) return LBM_EINVAL;
+  if (!rho || !T) { ctx->err = "rho and T are required"; return LBM_EINVAL; }
+  const long long N = ncells(ctx->p);
+  const long long slab = std::min(kSlab, N);
+  double* srho = ctx->staging;
+  double* su = srho + slab;
+  double* sT = su + 3 * slab;
+  for (long long c0 = 0; c0 < N; c0 += slab) {
+    const long long len = std::min(slab, N - c0);
+    HIPCHK(ctx, hipMemcpyAsync(srho, rho + c0, len * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(sT, T + c0, len * 8, hipMemcpyHostToDevice, ctx->stream));
+    if (u) {
+      for (int a = 0; a < 3; ++a)
+        HIPCHK(ctx, hipMemcpyAsync(su + a * len, u + a * N + c0, len * 8, hipMemcpyHostToDevice, ctx->stream));
+    }
+    HIPCHK(ctx, dispatch(ctx, [&](auto impl) {
+      return decltype(impl)::init_slab(ctx, srho, u ? su : nullptr, sT, c0, len);
+    }));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  HIPCHK(ctx, hipMemsetAsync(ctx->flag, 0, 64, ctx->stream));
+  ctx->initialised = true;
+  ctx->step = 0;
+  double sums[RED_VALUES];
+  const lbm_status s = reduce_now(ctx, sums);
+  if (s != LBM_OK) return s;
+  ctx->mass0 = sums[0];
+  return LBM_OK;
+}
+
+lbm_status lbm_set_wall_T(lbm_ctx* ctx, int32_t face, const double* Tw) {
+  if (!ctx) return LBM_EINVAL;
+  if (face != 4 && face != 5) { ctx->err = "wall temperature fields exist for faces 4 and 5"; return LBM_EINVAL; }
+  if (ctx->p.face[face] != LBM_FACE_WALL) { ctx->err = "face is not a wall"; return LBM_EINVAL; }
+  const int k = face - 4;
+  if (!Tw) { ctx->has_Tw[k] = false; return LBM_OK; }
+  const size_t n = (size_t)ctx->p.nx * ctx->p.ny;
+  for (size_t i = 0; i < n; ++i)
+    if (!(Tw[i] > 0) || !std::isfinite(Tw[i])) { ctx->err = "wall temperatures must be positive"; return LBM_EINVAL; }
+  HIPCHK(ctx, hipMemcpyAsync(ctx->Tw[k], Tw, n * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->has_Tw[k] = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_kappa(lbm_ctx* ctx, double kappa_w) {
+  if (!ctx) return LBM_EINVAL;
+  if (!std::isfinite(kappa_w)) { ctx->err = "kappa_w must be finite"; return LBM_EINVAL; }
+  ctx->p.kappa_w = kappa_w;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps) {
+  if (!ctx) return LBM_EINVAL;
+  if (nsteps < 0) { ctx->err = "nsteps must be >= 0"; return LBM_EINVAL; }
+  if (!ctx->initialised) { ctx->err = "lbm_step before lbm_init"; return LBM_ESTATE; }
+  for (int s = 0; s < nsteps; ++s) {
+    HIPCHK(ctx, dispatch(ctx, [&](auto impl) { return decltype(impl)::step(ctx); }));
+    ctx->step++;
+  }
+  int flag = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&flag, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (flag) { ctx->err = "non-physical state (rho, T or psi out of range, or NaN)"; return LBM_ENONPHYS; }
+  return LBM_OK;
+}
+
+lbm_status lbm_fields(lbm_ctx* ctx, double* rho, double* u, double* T, int32_t dst_on_device) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->initialised) { ctx->err = "lbm_fields before lbm_init"; return LBM_ESTATE; }
+  HIPCHK(ctx, dispatch(ctx, [&](auto impl) { return decltype(impl)::prepass(ctx); }));
+  const long long N = ncells(ctx->p);
+  if (dst_on_device) {
+    HIPCHK(ctx, dispatch(ctx, [&](auto impl) { return decltype(impl)::fields_slab(ctx, rho, u, T, 0, N, N); }));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+  }
+  const long long slab = std::min(kSlab, N);
+  double* srho = ctx->staging;
+  double* su = srho + slab;
+  double* sT = su + 3 * slab;
+  for (long long c0 = 0; c0 < N; c0 += slab) {
+    const long long len = std::min(slab, N - c0);
+    HIPCHK(ctx, dispatch(ctx, [&](auto impl) {
+      return decltype(impl)::fields_slab(ctx, rho ? srho : nullptr, u ? su : nullptr, T ? sT : nullptr, c0, len, len);
+    }));
+    if (rho) HIPCHK(ctx, hipMemcpyAsync(rho + c0, srho, len * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (T) HIPCHK(ctx, hipMemcpyAsync(T + c0, sT, len * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (u)
+      for (int a = 0; a < 3; ++a)
+        HIPCHK(ctx, hipMemcpyAsync(u + a * N + c0, su + a * len, len * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_populations(lbm_ctx* ctx, double* f, double* g) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->initialised) { ctx->err = "lbm_populations before lbm_init"; return LBM_ESTATE; }
+  const long long N = ncells(ctx->p);
+  const long long slab = std::min(kSlab, N);
+  double* sf = ctx->staging;
+  double* sg = sf + 19 * slab;
+  for (long long c0 = 0; c0 < N; c0 += slab) {
+    const long long len = std::min(slab, N - c0);
+    HIPCHK(ctx, dispatch(ctx, [&](auto impl) {
+      return decltype(impl)::pops_slab(ctx, f ? sf : nullptr, g ? sg : nullptr, c0, len);
+    }));
+    if (f)
+      for (int i = 0; i < 19; ++i)
+        HIPCHK(ctx, hipMemcpyAsync(f + i * N + c0, sf + i * len, len * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (g)
+      for (int i = 0; i < 7; ++i)
+        HIPCHK(ctx, hipMemcpyAsync(g + i * N + c0, sg + i * len, len * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_reduce(lbm_ctx* ctx, lbm_diag* out) {
+  if (!ctx || !out) return LBM_EINVAL;
+  if (!ctx->initialised) { ctx->err = "lbm_reduce before lbm_init"; return LBM_ESTATE; }
+  double sums[RED_VALUES];
+  const lbm_status s = reduce_now(ctx, sums);
+  if (s != LBM_OK) return s;
+  out->mass = sums[0];
+  out->energy = sums[1];
+  out->vol_hard = sums[2];
+  out->vol_smooth = sums[3];
+  out->evap_mass = ctx->mass0 - sums[0];
+  out->step = ctx->step;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+void lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->owns && ctx->base) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->base);
+  }
+  delete ctx;
+}
+
+}  // extern "C"

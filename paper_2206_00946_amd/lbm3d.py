@@ -1,0 +1,243 @@
+"""Python binding of liblbm3d.so (argument marshalling only).
+
+Every step of the update runs in the HIP library; torch only provides device
+memory and the stream.  Importing this module fails loudly if the library
+has not been built (``python -c "import __graft_entry__ as g; g.build()"``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm3d.so")
+
+FP64, FP32_DEV, FP16_DEV, BF16_DEV = 0, 1, 2, 3
+PERIODIC, WALL, PRESSURE = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32_DEV, "fp16": FP16_DEV, "bf16": BF16_DEV}
+
+STATUS = {0: "LBM_OK", 1: "LBM_EINVAL", 2: "LBM_ENOMEM", 3: "LBM_EHIP", 4: "LBM_ENONPHYS",
+          5: "LBM_ESTATE", 6: "LBM_EUNSUPPORTED"}
+
+
+class LbmParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("omega", ctypes.c_double),
+        ("G", ctypes.c_double),
+        ("s_e", ctypes.c_double), ("s_nu", ctypes.c_double), ("s_q", ctypes.c_double), ("s_pi", ctypes.c_double),
+        ("wbar", ctypes.c_double), ("lambda_", ctypes.c_double), ("cv", ctypes.c_double),
+        ("s_T_other", ctypes.c_double),
+        ("theta_corr", ctypes.c_int32),
+        ("face", ctypes.c_int32 * 6),
+        ("face_T", ctypes.c_double * 6),
+        ("face_rho", ctypes.c_double * 6),
+        ("kappa_w", ctypes.c_double),
+        ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+        ("diag_rho_v", ctypes.c_double), ("diag_rho_l", ctypes.c_double),
+    ]
+
+
+class LbmDiag(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("energy", ctypes.c_double), ("vol_hard", ctypes.c_double),
+                ("vol_smooth", ctypes.c_double), ("evap_mass", ctypes.c_double), ("step", ctypes.c_int64)]
+
+
+EXPORTS = ["lbm_default_params", "lbm_required_bytes", "lbm_create", "lbm_init", "lbm_set_wall_T",
+           "lbm_set_kappa", "lbm_step", "lbm_fields", "lbm_populations", "lbm_reduce", "lbm_last_error",
+           "lbm_destroy"]
+
+_lib = None
+
+
+def load_library():
+    """Load liblbm3d.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    dp = P(ctypes.c_double)
+    lib.lbm_default_params.argtypes = [P(LbmParams), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.lbm_required_bytes.argtypes = [P(LbmParams), P(ctypes.c_size_t), P(ctypes.c_size_t)]
+    lib.lbm_create.argtypes = [P(LbmParams), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                               P(ctypes.c_void_p)]
+    lib.lbm_init.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    lib.lbm_set_wall_T.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
+    lib.lbm_set_kappa.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    lib.lbm_step.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.lbm_fields.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    lib.lbm_populations.argtypes = [ctypes.c_void_p, dp, dp]
+    lib.lbm_reduce.argtypes = [ctypes.c_void_p, P(LbmDiag)]
+    lib.lbm_last_error.argtypes = [ctypes.c_void_p]
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    lib.lbm_destroy.argtypes = [ctypes.c_void_p]
+    lib.lbm_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("lbm_last_error", "lbm_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_params(nx, ny, nz, precision="fp32", faces: Sequence[int] = (PERIODIC,) * 6, face_T=None,
+                face_rho=None, kappa_w=0.0, rho_ref=None, T_ref=None, diag_rho_v=None, diag_rho_l=None,
+                **overrides) -> LbmParams:
+    lib = load_library()
+    p = LbmParams()
+    lib.lbm_default_params(ctypes.byref(p), nx, ny, nz)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    for k in range(6):
+        p.face[k] = int(faces[k])
+        if face_T is not None:
+            p.face_T[k] = float(face_T[k])
+        if face_rho is not None:
+            p.face_rho[k] = float(face_rho[k])
+    p.kappa_w = float(kappa_w)
+    if rho_ref is not None:
+        p.rho_ref = float(rho_ref)
+    if T_ref is not None:
+        p.T_ref = float(T_ref)
+    if diag_rho_v is not None:
+        p.diag_rho_v = float(diag_rho_v)
+    if diag_rho_l is not None:
+        p.diag_rho_l = float(diag_rho_l)
+    for k, v in overrides.items():
+        setattr(p, "lambda_" if k == "lam" else k, v)
+    return p
+
+
+def params_from_workload(w: Dict, precision="fp32") -> LbmParams:
+    return make_params(w["nx"], w["ny"], w["nz"], precision=precision, faces=w["faces"], face_T=w["face_T"],
+                       face_rho=w["face_rho"], kappa_w=w["kappa_w"], rho_ref=w["rho_ref"], T_ref=w["T_ref"],
+                       diag_rho_v=w["rho_v"], diag_rho_l=w["rho_l"])
+
+
+class Lbm3D:
+    """One simulation context on the current torch CUDA (HIP) device.
+
+    The device buffer is a torch uint8 tensor owned by this object; the
+    library enqueues on torch's current stream at construction time.
+    """
+
+    def __init__(self, params: LbmParams, device: str = "cuda", torch_buffer: bool = True):
+        import torch
+
+        self.lib = load_library()
+        self.params = params
+        self.torch = torch
+        st = ctypes.c_size_t()
+        sc = ctypes.c_size_t()
+        self._check(self.lib.lbm_required_bytes(ctypes.byref(params), ctypes.byref(st), ctypes.byref(sc)), None)
+        self.state_bytes, self.scratch_bytes = st.value, sc.value
+        self.buffer = None
+        ptr = None
+        nbytes = 0
+        if torch_buffer:
+            self.buffer = torch.empty(st.value + sc.value + 256, dtype=torch.uint8, device=device)
+            base = self.buffer.data_ptr()
+            ptr = (base + 255) // 256 * 256
+            nbytes = st.value + sc.value
+        self.stream = torch.cuda.current_stream(torch.device(device))
+        ctx = ctypes.c_void_p()
+        self._check(self.lib.lbm_create(ctypes.byref(params), ptr, nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(ctx)), None)
+        self.ctx = ctx
+        self.n = params.nx * params.ny * params.nz
+        self.shape = (params.nz, params.ny, params.nx)
+
+    def _check(self, status, ctx):
+        if status != 0:
+            msg = self.lib.lbm_last_error(ctx.value if isinstance(ctx, ctypes.c_void_p) else ctx)
+            raise LbmError(status, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- API
+    def init(self, rho0: np.ndarray, T0: np.ndarray, u0: Optional[np.ndarray] = None):
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
+        T0 = np.ascontiguousarray(T0, dtype=np.float64).reshape(-1)
+        if rho0.size != self.n or T0.size != self.n:
+            raise ValueError("rho0 and T0 need nx*ny*nz values")
+        u = None
+        if u0 is not None:
+            u = np.ascontiguousarray(u0, dtype=np.float64).reshape(-1)
+            if u.size != 3 * self.n:
+                raise ValueError("u0 needs 3*nx*ny*nz values")
+        self._check(self.lib.lbm_init(self.ctx, _dptr(rho0), _dptr(u), _dptr(T0)), self.ctx)
+
+    def set_wall_T(self, face: int, Tw: Optional[np.ndarray]):
+        arr = None if Tw is None else np.ascontiguousarray(Tw, dtype=np.float64).reshape(-1)
+        if arr is not None and arr.size != self.params.nx * self.params.ny:
+            raise ValueError("wall field needs nx*ny values")
+        self._check(self.lib.lbm_set_wall_T(self.ctx, int(face), _dptr(arr)), self.ctx)
+
+    def set_kappa(self, kappa_w: float):
+        self._check(self.lib.lbm_set_kappa(self.ctx, float(kappa_w)), self.ctx)
+
+    def step(self, nsteps: int = 1):
+        self._check(self.lib.lbm_step(self.ctx, int(nsteps)), self.ctx)
+
+    def fields(self):
+        rho = np.empty(self.n)
+        u = np.empty(3 * self.n)
+        T = np.empty(self.n)
+        self._check(self.lib.lbm_fields(self.ctx, rho.ctypes.data, u.ctypes.data, T.ctypes.data, 0), self.ctx)
+        return rho.reshape(self.shape), u.reshape((3,) + self.shape), T.reshape(self.shape)
+
+    def fields_device(self):
+        """Fields into torch float64 tensors on the device (no host copy)."""
+        t = self.torch
+        dev = self.buffer.device if self.buffer is not None else "cuda"
+        rho = t.empty(self.n, dtype=t.float64, device=dev)
+        u = t.empty(3 * self.n, dtype=t.float64, device=dev)
+        T = t.empty(self.n, dtype=t.float64, device=dev)
+        self._check(self.lib.lbm_fields(self.ctx, rho.data_ptr(), u.data_ptr(), T.data_ptr(), 1), self.ctx)
+        return rho.view(self.shape), u.view((3,) + self.shape), T.view(self.shape)
+
+    def populations(self):
+        f = np.empty(19 * self.n)
+        g = np.empty(7 * self.n)
+        self._check(self.lib.lbm_populations(self.ctx, _dptr(f), _dptr(g)), self.ctx)
+        return f.reshape((19,) + self.shape), g.reshape((7,) + self.shape)
+
+    def reduce(self) -> Dict[str, float]:
+        d = LbmDiag()
+        self._check(self.lib.lbm_reduce(self.ctx, ctypes.byref(d)), self.ctx)
+        return dict(mass=d.mass, energy=d.energy, vol_hard=d.vol_hard, vol_smooth=d.vol_smooth,
+                    evap_mass=d.evap_mass, step=d.step)
+
+
+def from_workload(w: Dict, precision="fp32", device="cuda") -> Lbm3D:
+    sim = Lbm3D(params_from_workload(w, precision), device=device)
+    sim.init(w["rho0"], w["T0"])
+    for face, field in (w.get("Tw") or {}).items():
+        sim.set_wall_T(face, field)
+    return sim

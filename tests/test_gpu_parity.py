@@ -1,0 +1,240 @@
+"""GPU (HIP library, through the C ABI) against the FP64 oracle.
+
+FP64 storage must agree with the oracle to 1e-12 (max relative error for rho
+and T, normwise for u).  FP32 deviation storage must keep density within
+1e-4.  FP16/BF16 storage errors are measured and bounded loosely.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lbm_oracle as O
+from tests.helpers import oracle_params, oracle_run, rel_err_scalar, rel_err_vector, sub_block
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2206_00946_amd as P
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    P.load_library()
+    return P
+
+
+def _small_workloads():
+    return {
+        "droplet_periodic_32": synth.droplet_periodic(n=32, R0=8.0, W=5.0, noise=1e-6, seed=1),
+        "droplet_open_37x34x29": synth.droplet_open(nx=37, ny=34, nz=29, R0=9.0),
+        "heated_wall_35x31x27": synth.heated_wall(nx=35, ny=31, nz=27, R0=10.0, Tw_jitter=0.02, seed=5,
+                                                  kappa_w=0.3),
+        "blobs_closed_40x36x30": synth.blobs_closed(nx=40, ny=36, nz=30, mean_blobs=3, rmin=5.0, rmax=9.0),
+    }
+
+
+SMALL = _small_workloads()
+
+
+def _compare(name, got, ref, tol_r, tol_u, tol_T):
+    er = rel_err_scalar(got[0], ref[0])
+    eu = rel_err_vector(got[1], ref[1])
+    eT = rel_err_scalar(got[2], ref[2])
+    _log(f"{name}: rho {er:.3e}  u {eu:.3e}  T {eT:.3e}")
+    assert er < tol_r and eu < tol_u and eT < tol_T, (er, eu, eT)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_fp64_parity_small(P, name):
+    w = SMALL[name]
+    steps = 500 if name.startswith("droplet_periodic") else 60
+    record = (0, 1, 10, steps) if steps > 10 else (0, 1, steps)
+    _log(f"[fp64 parity] {name} steps={steps}")
+    ref = oracle_run(w, steps, record=record)
+    sim = P.from_workload(w, precision="fp64")
+    done = 0
+    for s in sorted(ref):
+        sim.step(s - done)
+        done = s
+        _compare(f"{name} step {s}", sim.fields(), ref[s], TOL64, TOL64, TOL64)
+    sim.close()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_fp32_deviation_parity_small(P, name):
+    w = SMALL[name]
+    steps = 200 if name.startswith("droplet_periodic") else 60
+    _log(f"[fp32 parity] {name} steps={steps}")
+    ref = oracle_run(w, steps, record=(1, steps))
+    sim = P.from_workload(w, precision="fp32")
+    sim.step(1)
+    _compare(f"{name} fp32 step 1", sim.fields(), ref[1], 1e-5, 1e-3, 1e-5)
+    sim.step(steps - 1)
+    _compare(f"{name} fp32 step {steps}", sim.fields(), ref[steps], 1e-4, 2e-2, 1e-4)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_half_storage_measured(P, prec):
+    """Narrow storage: finite and within a loose bound after 20 steps; the
+    measured errors are printed."""
+    w = SMALL["droplet_periodic_32"]
+    ref = oracle_run(w, 20, record=(20,))
+    sim = P.from_workload(w, precision=prec)
+    sim.step(20)
+    rho, u, T = sim.fields()
+    assert np.isfinite(rho).all() and np.isfinite(T).all()
+    er = rel_err_scalar(rho, ref[20][0])
+    eT = rel_err_scalar(T, ref[20][2])
+    _log(f"{prec}: rho {er:.3e} T {eT:.3e}")
+    assert er < (0.02 if prec == "fp16" else 0.1) and eT < (0.02 if prec == "fp16" else 0.1)
+    sim.close()
+
+
+def test_zero_steps_and_initial_fields(P):
+    w = SMALL["droplet_open_37x34x29"]
+    ref = oracle_run(w, 0, record=(0,))
+    sim = P.from_workload(w, precision="fp64")
+    sim.step(0)
+    _compare("step 0", sim.fields(), ref[0], TOL64, TOL64, TOL64)
+    rho_d, u_d, T_d = sim.fields_device()
+    assert np.array_equal(rho_d.cpu().numpy(), sim.fields()[0])
+    sim.close()
+
+
+def test_reductions_fp64(P):
+    """FP64 mass, energy and liquid-volume reductions against the oracle."""
+    w = SMALL["heated_wall_35x31x27"]
+    ref = oracle_run(w, 30, record=(0, 30))
+    p = oracle_params(w)
+    sim = P.from_workload(w, precision="fp64")
+    d0 = sim.reduce()
+    sim.step(30)
+    d = sim.reduce()
+    r0 = O.diagnostics(ref[0][0], ref[0][2], p, w["rho_v"], w["rho_l"])
+    r = O.diagnostics(ref[30][0], ref[30][2], p, w["rho_v"], w["rho_l"])
+    for k in ("mass", "energy", "vol_smooth"):
+        assert abs(d0[k] - r0[k]) <= 1e-12 * abs(r0[k]), k
+        assert abs(d[k] - r[k]) <= 1e-12 * abs(r[k]), k
+    assert d["vol_hard"] == r["vol_hard"]
+    assert abs(d["evap_mass"] - (r0["mass"] - r["mass"])) < 1e-9 * r0["mass"]
+    assert d["step"] == 30
+    sim.close()
+
+
+def test_determinism_bitwise(P):
+    w = SMALL["blobs_closed_40x36x30"]
+    outs = []
+    for _ in range(2):
+        sim = P.from_workload(w, precision="fp32")
+        sim.step(25)
+        outs.append(sim.fields())
+        outs[-1] = outs[-1] + (sim.reduce()["mass"],)
+        sim.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_closed_box_mass_conservation_fp64(P):
+    """No-slip walls on both z faces conserve mass (bounce-back)."""
+    w = SMALL["blobs_closed_40x36x30"]
+    sim = P.from_workload(w, precision="fp64")
+    m0 = sim.reduce()["mass"]
+    sim.step(50)
+    m1 = sim.reduce()["mass"]
+    assert abs(m1 - m0) / m0 < 1e-13
+
+
+def test_error_paths(P):
+    import ctypes
+    p = P.make_params(8, 8, 8, precision="fp64")
+    sim = P.Lbm3D(p)
+    with pytest.raises(P.LbmError) as e:
+        sim.step(1)
+    assert e.value.status == 5            # LBM_ESTATE
+    bad = P.make_params(8, 8, 8, faces=(0, 2, 0, 0, 0, 0))
+    with pytest.raises(P.LbmError) as e:
+        P.Lbm3D(bad)
+    assert e.value.status == 1            # LBM_EINVAL
+    unsup = P.make_params(8, 8, 8, theta_corr=1)
+    with pytest.raises(P.LbmError) as e:
+        P.Lbm3D(unsup)
+    assert e.value.status == 6            # LBM_EUNSUPPORTED
+    # a density beyond the psi^2 > 0 range at 0.86 Tc (both sides flag it)
+    w = synth.droplet_periodic(n=8, R0=2.0, noise=0.0)
+    w["rho0"][4, 4, 4] = 9.5
+    po = oracle_params(w)
+    f, g = O.init_populations(w["rho0"], w["T0"], po)
+    assert O.macroscopic(f, g, po)["bad"].any()
+    sim = P.from_workload(w, precision="fp64")
+    with pytest.raises(P.LbmError) as e:
+        sim.step(1)
+    assert e.value.status == 4            # LBM_ENONPHYS
+    sim.close()
+
+
+# ---------------------------------------------------------------- full sizes
+
+FULL = ["droplet_open_128", "heated_wall_256", "heated_wall_adjoint_96", "blobs_closed_512x512x384"]
+
+
+@functools.lru_cache(maxsize=1)
+def _full_workload(name):
+    return synth.named(name)
+
+
+def _sample_points(w, rng, n_random=6):
+    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    pts = [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))) for _ in range(n_random)]
+    pts += [(0, 0, 0), (nx - 1, ny // 2, nz - 1), (nx // 2, ny - 1, 0), (nx // 3, 1, nz // 2),
+            (nx // 2, ny // 2, 1), (nx - 2, ny - 2, nz - 2)]
+    # a few cells on the liquid-vapour interface
+    rho = w["rho0"]
+    mid = 0.5 * (w["rho_v"] + w["rho_l"])
+    zz, yy, xx = np.nonzero(np.abs(rho - mid) < 0.25 * (w["rho_l"] - w["rho_v"]))
+    if len(zz):
+        for k in rng.choice(len(zz), size=min(4, len(zz)), replace=False):
+            pts.append((int(xx[k]), int(yy[k]), int(zz[k])))
+    return pts
+
+
+@pytest.mark.parametrize("name", FULL)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_sampled(P, name, prec):
+    """Full-size workloads, the launch configuration the bench times: one step
+    on the GPU, compared at sampled cells with the oracle run on the
+    surrounding block (exact for cells far enough from the block's cut
+    sides)."""
+    _log(f"[full size] {name} {prec}: generating")
+    w = _full_workload(name)
+    rng = np.random.default_rng(7)
+    pts = _sample_points(w, rng)
+    _log(f"[full size] {name} {prec}: GPU step")
+    sim = P.from_workload(w, precision=prec)
+    sim.step(1)
+    rho, u, T = sim.fields()
+    sim.close()
+    del sim
+    tol_r, tol_u, tol_T = (TOL64, 1e-11, TOL64) if prec == "fp64" else (1e-5, 1e-3, 1e-5)
+    for (x, y, z) in pts:
+        b = sub_block(w, (x, y, z), half=9, margin=7)
+        ref = oracle_run(b, 1, record=(1,))[1]
+        lx, ly, lz = b["local"]
+        for a in range(3):
+            assert b["valid"][a][0] <= b["local"][a] < b["valid"][a][1]
+        er = abs(rho[z, y, x] - ref[0][lz, ly, lx]) / abs(ref[0][lz, ly, lx])
+        eT = abs(T[z, y, x] - ref[2][lz, ly, lx]) / abs(ref[2][lz, ly, lx])
+        scale = max(np.abs(ref[1]).max(), 1e-12)
+        eu = np.abs(u[:, z, y, x] - ref[1][:, lz, ly, lx]).max() / scale
+        assert er < tol_r and eT < tol_T and eu < tol_u, ((x, y, z), er, eu, eT)
+    _log(f"[full size] {name} {prec}: {len(pts)} cells ok")
