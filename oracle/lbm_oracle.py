@@ -10,8 +10,9 @@ Method: J. Huang, L. Wang, K. He, C. Huang, "An efficient thermal lattice
 Boltzmann method for simulating three-dimensional liquid-vapor phase change"
 (arXiv 2206.00946).  Every function cites the section / equation it restates.
 All arithmetic is float64, vectorised with numpy over the whole grid; the only
-library primitives used are matrix products (the moment transforms) and a
-matrix inverse (of the printed transforms).
+library primitives used are matrix products (the moment transforms).  The
+inverse transforms are computed exactly in rationals from the printed
+integer matrices and rounded once per entry.
 
 Array layout: populations are (Q, nz, ny, nx); fields are (nz, ny, nx);
 vectors are (3, nz, ny, nx) with components (x, y, z).  The flat cell index
@@ -51,6 +52,7 @@ from __future__ import annotations
 
 import warnings
 from dataclasses import dataclass
+from fractions import Fraction
 from typing import Dict, Optional, Sequence
 
 import numpy as np
@@ -107,10 +109,31 @@ C7 = M7[1:4].T.copy()                    # (7, 3)
 W19 = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
 CS2 = 1.0 / 3.0
 
+def exact_inverse(m: np.ndarray) -> np.ndarray:
+    """Inverse of an integer matrix by Gauss-Jordan elimination in exact
+    rationals, each entry then rounded once to the nearest double.  The
+    transforms of Appendix A are integer matrices with rational inverses;
+    a floating-point (LAPACK) inverse perturbs their entries by an ulp, which
+    breaks exact mass conservation of the collision at the 1e-16 level."""
+    n = len(m)
+    a = [[Fraction(int(v)) for v in row] + [Fraction(int(i == j)) for j in range(n)]
+         for i, row in enumerate(m)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if a[r][c] != 0)
+        a[c], a[piv] = a[piv], a[c]
+        pv = a[c][c]
+        a[c] = [v / pv for v in a[c]]
+        for r in range(n):
+            if r != c and a[r][c] != 0:
+                fac = a[r][c]
+                a[r] = [x - fac * y for x, y in zip(a[r], a[c])]
+    return np.array([[float(v) for v in row[n:]] for row in a])
+
+
 MHAT_F = MHAT.astype(np.float64)
-MHAT_INV = np.linalg.inv(MHAT_F)
+MHAT_INV = exact_inverse(MHAT)
 M7_F = M7.astype(np.float64)
-M7_INV = np.linalg.inv(M7_F)
+M7_INV = exact_inverse(M7)
 
 
 def opposite(c: np.ndarray) -> np.ndarray:

@@ -78,6 +78,14 @@ def test_transform_determinants_and_inverses():
     assert _frac_det(O.M7) == -24
     assert np.allclose(O.MHAT_F @ O.MHAT_INV, np.eye(19), atol=1e-14)
     assert np.allclose(O.M7_F @ O.M7_INV, np.eye(7), atol=1e-14)
+    # the inverses are rational with denominators dividing 12 (D3Q19) and 6
+    # (D3Q7): 12 M^-1 is an integer matrix and M (12 M^-1) = 12 I exactly
+    k19 = np.rint(12 * O.MHAT_INV).astype(np.int64)
+    assert np.abs(12 * O.MHAT_INV - k19).max() < 1e-13
+    assert np.array_equal(O.MHAT @ k19, 12 * np.eye(19, dtype=np.int64))
+    assert np.count_nonzero(k19) == 99
+    k7 = np.rint(6 * O.M7_INV).astype(np.int64)
+    assert np.array_equal(O.M7 @ k7, 6 * np.eye(7, dtype=np.int64))
 
 
 def test_d3q19_weights_isotropy():
