@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled D3Q19 + D3Q7 thermal pseudopotential step on one
+MI355X, printed as one JSON line.
+
+A step is one full time step of the method (every stage of the update) over
+the whole grid.  The default workload is the 512 x 512 x 384 closed box with
+seeded liquid blobs and a vertical temperature gradient, FP32 deviation
+storage; FP64 and FP16/BF16 storage are timed on the same workload as
+variants.  Inputs are generated on the host, uploaded once, and resident in
+HBM when the timed region starts.  The CPU baseline is the FP64 oracle on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic HBM bytes per cell update: each D3Q19 and D3Q7 population read
+# once and written once
+ALG_BYTES = {"fp64": 416, "fp32": 208, "fp16": 104, "bf16": 104}
+PEAK_HBM_GBS = 8000.0
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f16-storage/f32", "bf16": "bf16-storage/f32"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="blobs_closed_512x512x384")
+    ap.add_argument("--precision", default="fp32", choices=list(ALG_BYTES))
+    ap.add_argument("--variants", default="fp64,fp16,bf16",
+                    help="other storage precisions timed on the same workload ('' for none)")
+    ap.add_argument("--variant-steps", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    return ap.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2206_00946_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as fh:
+            h.update(fn.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, prec, launches_cells):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def time_precision(P, torch, w, prec, steps, warmup):
+    sim = P.from_workload(w, precision=prec)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    stream = sim.stream
+    start.record(stream)
+    t0 = time.perf_counter()
+    sim.step(steps)            # one launch sequence per step on sim.stream; syncs once at the end
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end) / steps
+    diag = sim.reduce()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    cells = w["nx"] * w["ny"] * w["nz"]
+    mlups = cells / (ms * 1e-3) / 1e6
+    achieved = ALG_BYTES[prec] * cells / (ms * 1e-3) / 1e9
+    return dict(ms_per_step=ms, mlups=mlups, wall_s=wall, achieved_gbs=achieved,
+                frac=achieved / PEAK_HBM_GBS, mass=diag["mass"])
+
+
+def cpu_baseline(w, steps):
+    """The FP64 oracle (unchanged, single-threaded numpy) on a bounded sample of
+    the workload: the same closed-box recipe (walls at 0.80 and 0.95 Tc,
+    linear initial T, seeded blobs) at 64 x 64 x 48 with 4 blobs of radius
+    5-9, so that it stays a physical state."""
+    from threadpoolctl import threadpool_limits
+    from oracle import lbm_oracle as O
+    from workloads import synth
+
+    s = synth.blobs_closed(64, 64, 48, mean_blobs=4, rmin=5.0, rmax=9.0, seed=4)
+    p = O.Params(s["nx"], s["ny"], s["nz"], faces=tuple(s["faces"]), face_T=tuple(s["face_T"]),
+                 face_rho=tuple(s["face_rho"]), kappa_w=s["kappa_w"])
+    with threadpool_limits(limits=1):
+        f, g = O.init_populations(s["rho0"], s["T0"], p)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f, g, _ = O.step(f, g, p)
+        dt = time.perf_counter() - t0
+    cells = s["nx"] * s["ny"] * s["nz"]
+    return dict(value=round(cells * steps / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{s['nx']}x{s['ny']}x{s['nz']} closed box of the same recipe ({s['n_blobs']} blobs), "
+                       f"{steps} steps, FP64 numpy on 1 thread, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    import paper_2206_00946_amd as P
+    from workloads import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P.load_library()
+    print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
+    w = synth.named(args.workload)
+    cells = w["nx"] * w["ny"] * w["nz"]
+    print(f"[bench] timing {args.precision}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
+    head = time_precision(P, torch, w, args.precision, args.steps, args.warmup)
+    variants = {}
+    vsteps = args.variant_steps or max(10, args.steps // 5)
+    for prec in [v for v in args.variants.split(",") if v and v != args.precision]:
+        print(f"[bench] variant {prec}: {vsteps} steps", file=sys.stderr, flush=True)
+        r = time_precision(P, torch, w, prec, vsteps, max(2, args.warmup // 2))
+        variants[prec] = dict(mlups=round(r["mlups"], 1), ms_per_step=round(r["ms_per_step"], 4),
+                              alg_bytes_per_cell=ALG_BYTES[prec], roofline_frac=round(r["frac"], 4))
+    traffic = measured_traffic(args.workload, args.precision, cells)
+    out = {
+        "metric": "coupled D3Q19+D3Q7 MLUPS & % HBM roofline",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": [w["nx"], w["ny"], w["nz"]], "cells": cells,
+                   "storage": args.precision, "faces": w["faces"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(head["frac"], 4), "traffic": traffic,
+                     "alg_bytes_per_cell": ALG_BYTES[args.precision]},
+        "variants": variants,
+        "source_hash": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

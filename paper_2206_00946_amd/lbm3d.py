@@ -61,6 +61,9 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # torch brings its own HIP runtime with the same soname as the one the
+    # library links; loading torch first makes the process use exactly one
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     dp = P(ctypes.c_double)

@@ -225,7 +225,9 @@ def test_full_size_sampled(P, name, prec):
     rho, u, T = sim.fields()
     sim.close()
     del sim
-    tol_r, tol_u, tol_T = (TOL64, 1e-11, TOL64) if prec == "fp64" else (1e-5, 1e-3, 1e-5)
+    # u is compared in absolute terms: |u| <= 0.1 everywhere, and a block far
+    # from any interface has no meaningful local scale
+    tol_r, tol_u, tol_T = (TOL64, 1e-13, TOL64) if prec == "fp64" else (1e-5, 2e-6, 1e-5)
     for (x, y, z) in pts:
         b = sub_block(w, (x, y, z), half=9, margin=7)
         ref = oracle_run(b, 1, record=(1,))[1]
@@ -234,7 +236,6 @@ def test_full_size_sampled(P, name, prec):
             assert b["valid"][a][0] <= b["local"][a] < b["valid"][a][1]
         er = abs(rho[z, y, x] - ref[0][lz, ly, lx]) / abs(ref[0][lz, ly, lx])
         eT = abs(T[z, y, x] - ref[2][lz, ly, lx]) / abs(ref[2][lz, ly, lx])
-        scale = max(np.abs(ref[1]).max(), 1e-12)
-        eu = np.abs(u[:, z, y, x] - ref[1][:, lz, ly, lx]).max() / scale
+        eu = np.abs(u[:, z, y, x] - ref[1][:, lz, ly, lx]).max()
         assert er < tol_r and eT < tol_T and eu < tol_u, ((x, y, z), er, eu, eT)
     _log(f"[full size] {name} {prec}: {len(pts)} cells ok")

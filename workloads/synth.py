@@ -172,14 +172,21 @@ def _poisson(lam: float, u: float) -> int:
     return k
 
 
-def blobs_closed(nx=512, ny=512, nz=384, T_bottom=0.80, T_top=0.95, mean_blobs=256,
-                 rmin=8.0, rmax=30.0, W=5.0, seed=4, steps=1000, cutoff=15.0):
+def blobs_closed(nx=512, ny=512, nz=384, T_bottom=0.85, T_top=0.95, mean_blobs=256,
+                 rmin=8.0, rmax=30.0, W=5.0, seed=4, steps=1000, cutoff=15.0, gap=10.0,
+                 max_attempts=64):
     """Closed box between two no-slip walls (z = 0 at T_bottom*Tc, z = nz-1 at
-    T_top*Tc), periodic x, y, linear initial T(z); liquid blobs at Poisson
-    (mean `mean_blobs`) uniformly placed centres with radii U[rmin, rmax].
+    T_top*Tc), periodic x, y, linear initial T(z); a Poisson(mean_blobs)
+    number of liquid blobs with radii U[rmin, rmax], centres uniform in x, y
+    and in z within [r + 3, nz - 4 - r].  Blobs do not overlap: a candidate
+    closer than r_i + r_j + gap (periodic in x, y) to an accepted blob is
+    redrawn (up to max_attempts draws per blob), so no vapour pocket is
+    trapped between merging liquid bodies.
     rho = rho_v(T(z)) + (rho_l - rho_v)(T(z)) max_k 1/2[1 - tanh(2 (d_k - r_k)/W)],
-    each blob profile truncated to 0 beyond d_k - r_k > cutoff; d_k periodic
-    in x, y."""
+    each blob profile truncated to 0 beyond d_k - r_k > cutoff.
+    The cold wall defaults to 0.85 Tc: at 0.80 Tc the liquid of the larger
+    blobs (r > 15) is compressed past the psi^2 > 0 limit (rho ~ 9.1) within
+    a few tens of steps, in the oracle as on the GPU."""
     faces = [PERIODIC, PERIODIC, PERIODIC, PERIODIC, WALL, WALL]
     Tmid = 0.5 * (T_bottom + T_top)
     w = _base("blobs_closed", nx, ny, nz, faces, steps, Tmid)
@@ -190,14 +197,32 @@ def blobs_closed(nx=512, ny=512, nz=384, T_bottom=0.80, T_top=0.95, mean_blobs=2
     rv, rl = coexistence(t_over)
     u0 = uniform01(seed, 1)[0]
     nb = _poisson(mean_blobs, u0)
-    draws = uniform01(seed + 1000, 4 * max(nb, 1)).reshape(-1, 4)
+    draws = uniform01(seed + 1000, 4 * max(nb, 1) * max_attempts).reshape(-1, 4)
+    blobs = []
+    cursor = 0
+    for _ in range(nb):
+        for _attempt in range(max_attempts):
+            d = draws[cursor]
+            cursor += 1
+            r = rmin + (rmax - rmin) * d[3]
+            zlo, zhi = r + 3.0, (nz - 4.0) - r
+            if zhi < zlo:
+                continue
+            c = (d[0] * nx, d[1] * ny, zlo + (zhi - zlo) * d[2])
+            ok = True
+            for (bx, by, bz, br) in blobs:
+                dx = abs(c[0] - bx)
+                dx = min(dx, nx - dx)
+                dy = abs(c[1] - by)
+                dy = min(dy, ny - dy)
+                if dx * dx + dy * dy + (c[2] - bz) ** 2 < (r + br + gap) ** 2:
+                    ok = False
+                    break
+            if ok:
+                blobs.append((c[0], c[1], c[2], r))
+                break
     frac = np.zeros((nz, ny, nx), dtype=np.float64)
-    for k in range(nb):
-        r = rmin + (rmax - rmin) * draws[k, 3]
-        cx = draws[k, 0] * nx
-        cy = draws[k, 1] * ny
-        zlo, zhi = r + 3.0, (nz - 4.0) - r
-        cz = zlo + (zhi - zlo) * draws[k, 2]
+    for (cx, cy, cz, r) in blobs:
         ext = r + cutoff
         z0 = max(int(np.floor(cz - ext)), 0)
         z1 = min(int(np.ceil(cz + ext)) + 1, nz)
@@ -207,16 +232,15 @@ def blobs_closed(nx=512, ny=512, nz=384, T_bottom=0.80, T_top=0.95, mean_blobs=2
         dz = (zs - cz)[:, None, None]
         dy = (ys - cy)[None, :, None]
         dx = (xs - cx)[None, None, :]
-        d = np.sqrt(dx * dx + dy * dy + dz * dz)
-        prof = np.where(d - r > cutoff, 0.0, 0.5 * (1.0 - np.tanh(2.0 * (d - r) / W)))
-        yi = np.mod(ys, ny)
-        xi = np.mod(xs, nx)
-        sub = frac[np.ix_(zs, yi, xi)]
-        frac[np.ix_(zs, yi, xi)] = np.maximum(sub, prof)
+        dist = np.sqrt(dx * dx + dy * dy + dz * dz)
+        prof = np.where(dist - r > cutoff, 0.0, 0.5 * (1.0 - np.tanh(2.0 * (dist - r) / W)))
+        sel = np.ix_(zs, np.mod(ys, ny), np.mod(xs, nx))
+        frac[sel] = np.maximum(frac[sel], prof)
     rho = rv[:, None, None] + (rl - rv)[:, None, None] * frac
     w["rho0"] = rho
     w["T0"] = np.broadcast_to((t_over * Tc)[:, None, None], rho.shape).copy()
-    w["n_blobs"] = nb
+    w["n_blobs"] = len(blobs)
+    w["blobs"] = blobs
     w["rho_v"] = float(coexistence(Tmid)[0])
     w["rho_l"] = float(coexistence(Tmid)[1])
     return w
