@@ -1,4 +1,28 @@
-// Fused single-pass step (placeholder until the fast path lands).
+// Fused single-pass step: one kernel launch per time step reads every
+// population once and writes it once (Huang, Wang, He & Huang, arXiv
+// 2206.00946, Sec. 2 and 3.1).
+//
+// Domain: periodic in x and y; z periodic or bounded by two no-slip walls
+// with a 90 degree contact angle (kappa_w = 0, so the ghost psi of eq. (37)
+// mirrors the first interior layer).  nx must be a multiple of 64 and ny a
+// multiple of the tile height.  Other set-ups use the unfused kernels.
+//
+// A workgroup owns a 64 x TY column tile (one wavefront per row, one thread
+// per column) and marches through z.  For every plane p it loads the
+// populations of the tile plus a two-cell halo in x and y and keeps
+//   psi (eq. (7))           -> LDS ring of 3 planes, 2-cell halo
+//   rho, u_eq = j/rho       -> LDS rings, 1-cell halo
+// The interaction force of plane p-1 (eq. (6)) then gives the real velocity
+// u (eq. (5)) on a 1-cell halo, the D3Q19 MRT-EDM collision of plane p-1
+// (eq. (8)) and its push (eq. (9), bounce-back eq. (34)).  The divergence of
+// u is accumulated plane by plane, so the D3Q7 collision (eqs. (13)-(15))
+// runs on plane p-2.  The rho*c_v blend of eq. (13) needs the old g_i at the
+// destination: in-tile in-plane transfers are finished by the destination
+// one plane later (its own old value, the source's g* through LDS); transfers
+// leaving the tile use the halo's old values kept in a small LDS ring; z
+// transfers stay in the thread's column registers.
+// Dirichlet temperatures on wall nodes (eqs. (35)-(36)) are applied by a
+// small kernel on the wall planes before this one.
 #pragma once
 
 #include "lbm3d.h"
@@ -6,13 +30,426 @@
 
 namespace lbm {
 
-inline bool fused_supported(const lbm_params&) { return false; }
+constexpr int FTX = 64;
+
+template <typename C>
+struct FusedArgs {
+  Phys<C> ph;
+  int nx, ny, nz;
+  long long N;
+  int zwall;  // 1: no-slip walls at z = 0 and z = nz - 1; 0: periodic z
+  int tiles_x, ntiles, chunk;
+  int* flag;
+};
+
+template <int TY>
+struct Tile {
+  static constexpr int TX = FTX;
+  static constexpr int NT = TX * TY;
+  static constexpr int EX = TX + 4;
+  static constexpr int EY = TY + 4;
+  static constexpr int E2 = EX * EY;                  // tile + 2-cell halo
+  static constexpr int NH = E2 - NT;                  // halo cells
+  static constexpr int NR1 = (TX + 2) * (TY + 2) - NT;  // first halo ring
+  static constexpr int NGR = 2 * TX + 2 * TY;         // ring cells fed by in-plane D3Q7 links
+  static_assert(NT >= NH && NT >= NR1, "tile too small for one helper cell per thread");
+
+  __device__ static int interior_e(int tx, int ty) { return (ty + 2) * EX + tx + 2; }
+
+  // k-th cell of the 2-cell halo: two full rows below, 4 side cells per
+  // interior row, two full rows above
+  __device__ static void halo_cell(int k, int& ex, int& ey) {
+    if (k < 2 * EX) {
+      ey = k / EX;
+      ex = k % EX;
+    } else if (k < 2 * EX + 4 * TY) {
+      const int m = k - 2 * EX;
+      ey = 2 + m / 4;
+      const int c = m % 4;
+      ex = c < 2 ? c : EX - 4 + c;
+    } else {
+      const int m = k - 2 * EX - 4 * TY;
+      ey = TY + 2 + m / EX;
+      ex = m % EX;
+    }
+  }
+
+  // k-th cell of the first halo ring
+  __device__ static void ring1_cell(int k, int& ex, int& ey) {
+    if (k < TX + 2) {
+      ey = 1;
+      ex = 1 + k;
+    } else if (k < TX + 2 + 2 * TY) {
+      const int m = k - (TX + 2);
+      ey = 2 + m / 2;
+      ex = (m & 1) ? EX - 2 : 1;
+    } else {
+      ey = TY + 2;
+      ex = 1 + (k - (TX + 2) - 2 * TY);
+    }
+  }
+
+  // ring cell fed by an in-plane D3Q7 link leaving the tile: its slot in the
+  // ring of old values and the direction (1 +x, 2 -x, 3 +y, 4 -y), or -1
+  __device__ static int receiver(int ex, int ey, int& dir) {
+    if (ex == EX - 2 && ey >= 2 && ey < TY + 2) { dir = 1; return ey - 2; }
+    if (ex == 1 && ey >= 2 && ey < TY + 2) { dir = 2; return TY + ey - 2; }
+    if (ey == TY + 2 && ex >= 2 && ex < TX + 2) { dir = 3; return 2 * TY + ex - 2; }
+    if (ey == 1 && ex >= 2 && ex < TX + 2) { dir = 4; return 2 * TY + TX + ex - 2; }
+    dir = 0;
+    return -1;
+  }
+};
+
+__device__ __forceinline__ int wrapn(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+template <typename S, int TY>
+__global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, const S* __restrict__ gA,
+                                                   S* __restrict__ fB, S* __restrict__ gB,
+                                                   FusedArgs<typename Storage<S>::C> a) {
+  using C = typename Storage<S>::C;
+  using TL = Tile<TY>;
+  constexpr int TX = TL::TX, NT = TL::NT, EX = TL::EX, E2 = TL::E2;
+  __shared__ C s_psi[3][E2];
+  __shared__ C s_rho[4][E2];
+  __shared__ C s_ueq[2][3][E2];
+  __shared__ C s_u[3][E2];
+  __shared__ C s_gr[4][TL::NGR];
+  __shared__ C s_gs[4][NT];
+
+  const Phys<C> ph = a.ph;
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  int b = blockIdx.x;
+  const int nb = gridDim.x;
+  // consecutive tiles on one XCD (blocks are dealt to the 8 XCDs round-robin)
+  if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+  const int tile = b % a.ntiles, chunk = b / a.ntiles;
+  const int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
+  const int z0 = chunk * a.chunk, z1 = min(a.nz, z0 + a.chunk);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long long N = a.N;
+  const long long PS = (long long)nx * ny;
+  const int x = x0 + tx, y = y0 + ty;
+  const long long col = x + (long long)nx * y;
+  const int e_own = TL::interior_e(tx, ty);
+  const C inv_cv = C(1) / ph.cv;
+
+  // helper cells of this thread
+  int hex, hey;
+  TL::halo_cell(tid < TL::NH ? tid : 0, hex, hey);
+  const bool has_halo = tid < TL::NH;
+  const long long hcol = wrapn(x0 + hex - 2, nx) + (long long)nx * wrapn(y0 + hey - 2, ny);
+  const int he = hey * EX + hex;
+  int rdir;
+  const int ridx = TL::receiver(hex, hey, rdir);
+  int rex, rey;
+  TL::ring1_cell(tid < TL::NR1 ? tid : 0, rex, rey);
+  const bool has_ring = tid < TL::NR1;
+  const int re = rey * EX + rex;
+
+  C fa[19], fb[19], ga[7], gb[7], gc[7];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) fa[i] = fb[i] = C(0);
+#pragma unroll
+  for (int i = 0; i < 7; ++i) ga[i] = gb[i] = gc[i] = C(0);
+  C rho_a = C(1), rho_b = C(1), rho_c = C(1);
+  C ua[3] = {C(0), C(0), C(0)}, ub[3] = {C(0), C(0), C(0)};
+  C d0 = C(0), d1 = C(0), d2 = C(0);
+  C g6_old = C(0), pend_rho = C(1);
+  C pend_g[4] = {C(0), C(0), C(0), C(0)};
+  bool pend_valid = false;
+  int pend_z = 0;
+
+  auto plane_of = [&](int p, int& zp) -> bool {
+    if (a.zwall) {
+      zp = p;
+      return p >= 0 && p < nz;
+    }
+    zp = ((p % nz) + nz) % nz;
+    return true;
+  };
+
+  // in-tile in-plane D3Q7 transfers into the plane collided one iteration ago
+  auto finish_pulls = [&]() {
+    if (!pend_valid) return;
+    const long long cell = col + PS * pend_z;
+#pragma unroll
+    for (int i = 1; i <= 4; ++i) {
+      const int sx = tx - CX[i], sy = ty - CY[i];
+      if (sx < 0 || sx >= TX || sy < 0 || sy >= TY) continue;
+      const C gs = s_gs[i - 1][sy * TX + sx];
+      Storage<S>::store(gB + (long long)i * N + cell, pend_g[i - 1] + (gs - pend_g[i - 1]) * (inv_cv / pend_rho));
+    }
+  };
+
+  const int p_begin = z0 - 2, p_end = z1 + 1;
+  for (int p = p_begin; p <= p_end; ++p) {
+    const int k = p - p_begin;
+    const int s3 = k % 3, s4 = k & 3, s2 = k & 1;
+    int zp;
+    const bool exists = plane_of(p, zp);
+    // ---------------------------------------------------------------- load plane p
+    if (exists) {
+      const long long cell = col + PS * zp;
+      C sf = C(0), jx = C(0), jy = C(0), jz = C(0), sg = C(0);
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        fb[i] = Storage<S>::load(fA + (long long)i * N + cell);
+        sf += fb[i];
+        if (CX[i]) jx += C(CX[i]) * fb[i];
+        if (CY[i]) jy += C(CY[i]) * fb[i];
+        if (CZ[i]) jz += C(CZ[i]) * fb[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        gc[i] = Storage<S>::load(gA + (long long)i * N + cell);
+        sg += gc[i];
+      }
+      rho_c = ph.rho_ref + sf;
+      const C T = ph.T_ref + sg;
+      const C rad = psi_radicand(rho_c, T, ph);
+      if (nonphysical(rho_c, T, rad, ph)) a.flag[0] = 1;
+      s_psi[s3][e_own] = sqrt(rad);
+      s_rho[s4][e_own] = rho_c;
+      s_ueq[s2][0][e_own] = jx / rho_c;
+      s_ueq[s2][1][e_own] = jy / rho_c;
+      s_ueq[s2][2][e_own] = jz / rho_c;
+      if (has_halo) {
+        const long long hc = hcol + PS * zp;
+        C hs = C(0), hx = C(0), hy = C(0), hz = C(0), hg = C(0);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+          const C v = Storage<S>::load(fA + (long long)i * N + hc);
+          hs += v;
+          if (CX[i]) hx += C(CX[i]) * v;
+          if (CY[i]) hy += C(CY[i]) * v;
+          if (CZ[i]) hz += C(CZ[i]) * v;
+        }
+        C gv[7];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+          gv[i] = Storage<S>::load(gA + (long long)i * N + hc);
+          hg += gv[i];
+        }
+        const C hr = ph.rho_ref + hs;
+        const C hT = ph.T_ref + hg;
+        s_psi[s3][he] = sqrt(psi_radicand(hr, hT, ph));
+        s_rho[s4][he] = hr;
+        s_ueq[s2][0][he] = hx / hr;
+        s_ueq[s2][1][he] = hy / hr;
+        s_ueq[s2][2][he] = hz / hr;
+        if (ridx >= 0) s_gr[s4][ridx] = gv[rdir];
+      }
+    }
+    __syncthreads();
+    // ---------------------------------------------------------------- plane p-1: force, u, D3Q19
+    finish_pulls();
+    const int q = p - 1;
+    int zq;
+    const bool do_u = q >= z0 - 1 && plane_of(q, zq);
+    if (do_u) {
+      // psi slots of planes q-1, q, q+1 (walls: the ghost layer mirrors the
+      // first interior layer, eq. (37) with theta = 90 degrees)
+      int sm = (k + 1) % 3, s0 = (k + 2) % 3, sp = s3;
+      if (a.zwall && zq == 0) sm = sp;
+      if (a.zwall && zq == nz - 1) sp = sm;
+      const bool wall_plane = a.zwall && (zq == 0 || zq == nz - 1);
+      const int sq = (k + 1) & 1;  // ueq slot of plane q
+      const int rq = (k + 3) & 3;  // rho slot of plane q
+      auto force_at = [&](int e, C& Fx, C& Fy, C& Fz) {
+        C ax = C(0), ay = C(0), az = C(0);
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+          const C wgt = i < 7 ? C(1) / C(6) : C(1) / C(12);
+          const int slot = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
+          const C pn = s_psi[slot][e + CX[i] + CY[i] * EX];
+          if (CX[i]) ax += wgt * C(CX[i]) * pn;
+          if (CY[i]) ay += wgt * C(CY[i]) * pn;
+          if (CZ[i]) az += wgt * C(CZ[i]) * pn;
+        }
+        const C pc = -ph.G * s_psi[s0][e];
+        Fx = pc * ax;
+        Fy = pc * ay;
+        Fz = pc * az;
+      };
+      {
+        C Fx, Fy, Fz;
+        force_at(e_own, Fx, Fy, Fz);
+        const C rho = rho_b;
+        const C dux = Fx / rho, duy = Fy / rho, duz = Fz / rho;
+        C uex = s_ueq[sq][0][e_own], uey = s_ueq[sq][1][e_own], uez = s_ueq[sq][2][e_own];
+        if (wall_plane) {
+          uex = -C(0.5) * dux;
+          uey = -C(0.5) * duy;
+          uez = -C(0.5) * duz;
+        }
+        ub[0] = uex + C(0.5) * dux;
+        ub[1] = uey + C(0.5) * duy;
+        ub[2] = uez + C(0.5) * duz;
+        s_u[0][e_own] = ub[0];
+        s_u[1][e_own] = ub[1];
+        s_u[2][e_own] = ub[2];
+        if (q >= z0 && q < z1) {
+          collide19(fa, rho, rho - ph.rho_ref, uex, uey, uez, dux, duy, duz, ph);
+#pragma unroll
+          for (int i = 0; i < 19; ++i) {
+            const int xd = wrapn(x + CX[i], nx), yd = wrapn(y + CY[i], ny);
+            int zd = zq + CZ[i];
+            if (zd < 0 || zd >= nz) {
+              if (a.zwall) {
+                Storage<S>::store(fB + (long long)opp19(i) * N + col + PS * zq, fa[i]);
+                continue;
+              }
+              zd = wrapn(zd, nz);
+            }
+            Storage<S>::store(fB + (long long)i * N + xd + (long long)nx * yd + PS * zd, fa[i]);
+          }
+        }
+      }
+      if (has_ring) {
+        C Fx, Fy, Fz;
+        force_at(re, Fx, Fy, Fz);
+        const C rho = s_rho[rq][re];
+        C vx = s_ueq[sq][0][re] + C(0.5) * Fx / rho;
+        C vy = s_ueq[sq][1][re] + C(0.5) * Fy / rho;
+        C vz = s_ueq[sq][2][re] + C(0.5) * Fz / rho;
+        if (wall_plane) vx = vy = vz = C(0);
+        s_u[0][re] = vx;
+        s_u[1][re] = vy;
+        s_u[2][re] = vz;
+      }
+    }
+    __syncthreads();
+    // ---------------------------------------------------------------- divergence contributions of u(q)
+    if (do_u) {
+#pragma unroll
+      for (int i = 1; i < 19; ++i) {
+        const int e = e_own + CX[i] + CY[i] * EX;
+        const C c = C(3) * w19<C>(i) * (C(CX[i]) * s_u[0][e] + C(CY[i]) * s_u[1][e] + C(CZ[i]) * s_u[2][e]);
+        if (CZ[i] > 0) d0 += c;        // u(q) is the +z neighbour of plane q-1 = p-2
+        else if (CZ[i] == 0) d1 += c;  // in-plane neighbour of plane q
+        else d2 += c;                  // -z neighbour of plane q+1 = p
+      }
+    }
+    // ---------------------------------------------------------------- plane p-2: D3Q7
+    const int r = p - 2;
+    int zr;
+    const bool r_exists = plane_of(r, zr);
+    const C og1 = ga[1], og2 = ga[2], og3 = ga[3], og4 = ga[4], og6 = ga[6];
+    const bool do_g = r_exists && r >= z0 && r < z1;
+    if (do_g) {
+      const long long cell = col + PS * zr;
+      const C T = ph.T_ref + (ga[0] + ga[1] + ga[2] + ga[3] + ga[4] + ga[5] + ga[6]);
+      C gx, gy, gz;
+      local_gradT(ga, ph, gx, gy, gz);
+      const C rho = rho_a;
+      const C Fbar = rho * ph.cv * (ua[0] * gx + ua[1] * gy + ua[2] * gz) + T * pr_dpdT(rho, T, ph) * d0;
+      const C og0 = ga[0];
+      collide7(ga, Fbar, ph);
+      Storage<S>::store(gB + cell, og0 + (ga[0] - og0) * (inv_cv / rho));
+      // +z: destination is plane r+1 of this column (old value in gb)
+      {
+        int zd = zr + 1;
+        bool ok = true;
+        if (zd >= nz) {
+          if (a.zwall) ok = false; else zd = 0;
+        }
+        if (ok)
+          Storage<S>::store(gB + 5 * N + col + PS * zd, gb[5] + (ga[5] - gb[5]) * (inv_cv / rho_b));
+      }
+      // -z: destination is plane r-1 of this column (old value kept from last iteration)
+      {
+        int zd = zr - 1;
+        bool ok = true;
+        if (zd < 0) {
+          if (a.zwall) ok = false; else zd = nz - 1;
+        }
+        if (ok)
+          Storage<S>::store(gB + 6 * N + col + PS * zd, g6_old + (ga[6] - g6_old) * (inv_cv / pend_rho));
+      }
+      const int rs = (k + 2) & 3;  // rho / ring slot of plane r
+#pragma unroll
+      for (int i = 1; i <= 4; ++i) {
+        const int dx = tx + CX[i], dy = ty + CY[i];
+        if (dx >= 0 && dx < TX && dy >= 0 && dy < TY) {
+          s_gs[i - 1][tid] = ga[i];
+        } else {
+          const int slot = i == 1 ? ty : (i == 2 ? TY + ty : (i == 3 ? 2 * TY + tx : 2 * TY + TX + tx));
+          const C gold = s_gr[rs][slot];
+          const C rd = s_rho[rs][e_own + CX[i] + CY[i] * EX];
+          const long long dcell = wrapn(x + CX[i], nx) + (long long)nx * wrapn(y + CY[i], ny) + PS * zr;
+          Storage<S>::store(gB + (long long)i * N + dcell, gold + (ga[i] - gold) * (inv_cv / rd));
+        }
+      }
+    }
+    pend_valid = do_g;
+    pend_z = zr;
+    pend_g[0] = og1;
+    pend_g[1] = og2;
+    pend_g[2] = og3;
+    pend_g[3] = og4;
+    pend_rho = rho_a;
+    g6_old = og6;
+    // ---------------------------------------------------------------- rotate
+    d0 = d1;
+    d1 = d2;
+    d2 = C(0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) fa[i] = fb[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      ga[i] = gb[i];
+      gb[i] = gc[i];
+    }
+    rho_a = rho_b;
+    rho_b = rho_c;
+    ua[0] = ub[0];
+    ua[1] = ub[1];
+    ua[2] = ub[2];
+  }
+  __syncthreads();
+  finish_pulls();
+}
+
+inline int fused_tile_height(int precision) {
+  (void)precision;
+  return 8;
+}
+
+inline bool fused_supported(const lbm_params& p) {
+  for (int k = 0; k < 4; ++k)
+    if (p.face[k] != LBM_FACE_PERIODIC) return false;
+  const bool zper = p.face[4] == LBM_FACE_PERIODIC && p.face[5] == LBM_FACE_PERIODIC;
+  const bool zwall = p.face[4] == LBM_FACE_WALL && p.face[5] == LBM_FACE_WALL;
+  if (!zper && !zwall) return false;
+  if (zwall && p.kappa_w != 0.0) return false;
+  const int ty = fused_tile_height(p.precision);
+  if (p.nx % FTX != 0 || p.ny % ty != 0) return false;
+  if (p.nz < 4) return false;
+  return true;
+}
 
 template <typename S>
 struct FusedImpl {
-  static hipError_t step(const lbm_params&, hipStream_t, const S*, const S*, S*, S*, const double*, bool,
-                         const double*, bool, int*) {
-    return hipErrorNotSupported;
+  using C = typename Storage<S>::C;
+  static hipError_t step(const lbm_params& p, const Phys<C>& ph, hipStream_t stream, const S* fA, const S* gA, S* fB,
+                         S* gB, int* flag, int chunk_planes) {
+    FusedArgs<C> a;
+    a.ph = ph;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.N = (long long)p.nx * p.ny * p.nz;
+    a.zwall = p.face[4] == LBM_FACE_WALL;
+    constexpr int TY = 8;
+    a.tiles_x = p.nx / FTX;
+    a.ntiles = a.tiles_x * (p.ny / TY);
+    a.chunk = chunk_planes > 0 ? chunk_planes : p.nz;
+    const int nchunks = (p.nz + a.chunk - 1) / a.chunk;
+    a.flag = flag;
+    hipLaunchKernelGGL((k_fused<S, TY>), dim3(a.ntiles * nchunks), dim3(FTX * TY), 0, stream, fA, gA, fB, gB, a);
+    return hipGetLastError();
   }
 };
 

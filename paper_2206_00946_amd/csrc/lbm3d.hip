@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -63,6 +64,7 @@ struct lbm_ctx {
   int64_t step = 0;
   double mass0 = 0.0;
   bool fused_ok = false;
+  int fused_chunk = 0;  // z planes per workgroup of the fused kernel (0: all)
   std::string err;
 };
 
@@ -239,11 +241,19 @@ struct Impl {
     return hipGetLastError();
   }
 
+  static hipError_t step_fused(lbm_ctx* ctx) {
+    const lbm_params& p = ctx->p;
+    if (p.face[4] == LBM_FACE_WALL) {
+      // Dirichlet temperatures of the wall nodes (eqs. (35)-(36)) before the single pass
+      hipError_t e = thermal_dirichlet(ctx, (S*)ctx->gA);
+      if (e != hipSuccess) return e;
+    }
+    return FusedImpl<S>::step(p, phys_of<C>(p), ctx->stream, (const S*)ctx->fA, (const S*)ctx->gA, (S*)ctx->fB,
+                              (S*)ctx->gB, ctx->flag, ctx->fused_chunk);
+  }
+
   static hipError_t step(lbm_ctx* ctx) {
-    hipError_t e = ctx->fused_ok ? FusedImpl<S>::step(ctx->p, ctx->stream, (const S*)ctx->fA, (const S*)ctx->gA,
-                                                      (S*)ctx->fB, (S*)ctx->gB, ctx->Tw[0], ctx->has_Tw[0],
-                                                      ctx->Tw[1], ctx->has_Tw[1], ctx->flag)
-                                 : step_ref(ctx);
+    hipError_t e = ctx->fused_ok ? step_fused(ctx) : step_ref(ctx);
     if (e != hipSuccess) return e;
     std::swap(ctx->fA, ctx->fB);
     std::swap(ctx->gA, ctx->gB);
@@ -379,6 +389,17 @@ lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_by
   ctx->flag = (int*)(b + L.off_flag);
   ctx->staging = (double*)(b + L.off_stage);
   ctx->fused_ok = fused_supported(*p);
+  {
+    // enough workgroups to cover the 256 compute units twice, z chunks of >= 8 planes
+    const long long ntiles = (long long)(p->nx / FTX) * (p->ny / fused_tile_height(p->precision));
+    long long nchunks = ntiles > 0 ? (512 + ntiles - 1) / ntiles : 1;
+    nchunks = std::max(1ll, std::min(nchunks, (long long)p->nz / 8));
+    ctx->fused_chunk = (int)((p->nz + nchunks - 1) / nchunks);
+    if (const char* ev = std::getenv("LBM_FUSED")) {
+      if (ev[0] == '0') ctx->fused_ok = false;
+    }
+    if (const char* ev = std::getenv("LBM_FUSED_CHUNK")) ctx->fused_chunk = std::max(1, std::atoi(ev));
+  }
   hipError_t e = hipMemsetAsync(ctx->flag, 0, 64, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {

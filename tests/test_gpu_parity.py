@@ -239,3 +239,49 @@ def test_full_size_sampled(P, name, prec):
         eu = np.abs(u[:, z, y, x] - ref[1][:, lz, ly, lx]).max()
         assert er < tol_r and eT < tol_T and eu < tol_u, ((x, y, z), er, eu, eT)
     _log(f"[full size] {name} {prec}: {len(pts)} cells ok")
+
+
+# ---------------------------------------------------------------- fused single-pass kernel
+
+FUSED = {
+    "droplet_periodic_128x16x24": lambda: synth.droplet_periodic(nx=128, ny=16, nz=24, R0=6.0, W=5.0,
+                                                                 noise=1e-6, seed=2, center=(70, 8, 12)),
+    "blobs_closed_64x32x40": lambda: synth.blobs_closed(nx=64, ny=32, nz=40, mean_blobs=3, rmin=5.0,
+                                                        rmax=8.0, seed=9),
+}
+
+
+@pytest.mark.parametrize("chunk", ["", "5"])
+@pytest.mark.parametrize("name", list(FUSED))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_parity(P, name, prec, chunk, monkeypatch):
+    """The single-pass kernel (default for these shapes) against the oracle,
+    with the z range in one piece and cut into 5-plane chunks."""
+    monkeypatch.setenv("LBM_FUSED_CHUNK", chunk or "0")
+    if not chunk:
+        monkeypatch.delenv("LBM_FUSED_CHUNK")
+    w = FUSED[name]()
+    steps = 40
+    _log(f"[fused] {name} {prec} chunk={chunk or 'all'}")
+    ref = oracle_run(w, steps, record=(1, steps))
+    sim = P.from_workload(w, precision=prec)
+    tol = (TOL64, TOL64, TOL64) if prec == "fp64" else (1e-5, 1e-3, 1e-5)
+    sim.step(1)
+    _compare(f"{name} {prec} step 1", sim.fields(), ref[1], *tol)
+    sim.step(steps - 1)
+    tol = (TOL64, TOL64, TOL64) if prec == "fp64" else (1e-4, 2e-2, 1e-4)
+    _compare(f"{name} {prec} step {steps}", sim.fields(), ref[steps], *tol)
+    sim.close()
+
+
+@pytest.mark.parametrize("name", list(FUSED))
+def test_fused_matches_unfused_fp64(P, name, monkeypatch):
+    w = FUSED[name]()
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("LBM_FUSED", flag)
+        sim = P.from_workload(w, precision="fp64")
+        sim.step(15)
+        out.append(sim.fields())
+        sim.close()
+    _compare(f"{name} fused vs unfused", out[0], out[1], 1e-13, 1e-13, 1e-13)
