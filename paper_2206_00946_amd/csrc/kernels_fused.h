@@ -21,9 +21,12 @@
 // one plane later (its own old value, the source's g* through LDS); transfers
 // leaving the tile use the halo's old values kept in a small LDS ring; z
 // transfers stay in the thread's column registers.
-// Dirichlet temperatures on wall nodes (eqs. (35)-(36)) are applied by a
-// small kernel on the wall planes before this one.
+// Dirichlet temperatures on wall nodes (eqs. (35)-(36)) are applied to the
+// values loaded for a wall plane, from the next plane inward; a time step is
+// exactly one launch of this kernel.
 #pragma once
+
+#include <cstdlib>
 
 #include "lbm3d.h"
 #include "kernels_ref.h"
@@ -39,6 +42,8 @@ struct FusedArgs {
   long long N;
   int zwall;  // 1: no-slip walls at z = 0 and z = nz - 1; 0: periodic z
   int tiles_x, ntiles, chunk;
+  C wall_T[2];            // Dirichlet temperatures of the z = 0 and z = nz - 1 walls
+  const double* wall_Tw[2];  // optional per-cell wall temperature fields (nx*ny)
   int* flag;
 };
 
@@ -103,6 +108,20 @@ struct Tile {
 
 __device__ __forceinline__ int wrapn(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Population access with the plane-major layout: one buffer descriptor over
+// all directions of one plane (uniform, scalar registers), the direction as a
+// scalar byte offset (i * plane bytes) and the cell as a per-lane byte offset.
+template <typename S>
+__device__ __forceinline__ typename Storage<S>::C ld_at(const S* plane, unsigned bytes, unsigned voff,
+                                                        unsigned soff) {
+  return Buf<S>::load(buffer_range(plane, bytes), voff, soff);
+}
+template <typename S>
+__device__ __forceinline__ void st_at(S* plane, unsigned bytes, unsigned voff, unsigned soff,
+                                      typename Storage<S>::C v) {
+  Buf<S>::store(buffer_range(plane, bytes), voff, soff, v);
+}
+
 template <typename S, int TY>
 __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, const S* __restrict__ gA,
                                                    S* __restrict__ fB, S* __restrict__ gB,
@@ -131,7 +150,11 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   const long long N = a.N;
   const long long PS = (long long)nx * ny;
   const int x = x0 + tx, y = y0 + ty;
-  const long long col = x + (long long)nx * y;
+  constexpr unsigned ES = sizeof(S);
+  const unsigned col = (unsigned)(x + nx * y);
+  const unsigned colb = col * ES;
+  const unsigned PB = (unsigned)(nx * ny) * ES;  // bytes of one plane of one direction
+  const unsigned F19 = 19 * PB, G7 = 7 * PB;       // bytes of all directions of one plane
   const int e_own = TL::interior_e(tx, ty);
   const C inv_cv = C(1) / ph.cv;
 
@@ -139,7 +162,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   int hex, hey;
   TL::halo_cell(tid < TL::NH ? tid : 0, hex, hey);
   const bool has_halo = tid < TL::NH;
-  const long long hcol = wrapn(x0 + hex - 2, nx) + (long long)nx * wrapn(y0 + hey - 2, ny);
+  const unsigned hcol = (unsigned)(wrapn(x0 + hex - 2, nx) + nx * wrapn(y0 + hey - 2, ny));
+  const unsigned hcolb = hcol * ES;
   const int he = hey * EX + hex;
   int rdir;
   const int ridx = TL::receiver(hex, hey, rdir);
@@ -173,13 +197,13 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   // in-tile in-plane D3Q7 transfers into the plane collided one iteration ago
   auto finish_pulls = [&]() {
     if (!pend_valid) return;
-    const long long cell = col + PS * pend_z;
+    S* gz = gB + PS * 7 * pend_z;
 #pragma unroll
     for (int i = 1; i <= 4; ++i) {
       const int sx = tx - CX[i], sy = ty - CY[i];
       if (sx < 0 || sx >= TX || sy < 0 || sy >= TY) continue;
       const C gs = s_gs[i - 1][sy * TX + sx];
-      Storage<S>::store(gB + (long long)i * N + cell, pend_g[i - 1] + (gs - pend_g[i - 1]) * (inv_cv / pend_rho));
+      st_at(gz, G7, colb, i * PB, pend_g[i - 1] + (gs - pend_g[i - 1]) * (inv_cv / pend_rho));
     }
   };
 
@@ -191,11 +215,12 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     const bool exists = plane_of(p, zp);
     // ---------------------------------------------------------------- load plane p
     if (exists) {
-      const long long cell = col + PS * zp;
+      const S* fz = fA + PS * 19 * zp;
+      const S* gzp = gA + PS * 7 * zp;
       C sf = C(0), jx = C(0), jy = C(0), jz = C(0), sg = C(0);
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
-        fb[i] = Storage<S>::load(fA + (long long)i * N + cell);
+        fb[i] = ld_at(fz, F19, colb, i * PB);
         sf += fb[i];
         if (CX[i]) jx += C(CX[i]) * fb[i];
         if (CY[i]) jy += C(CY[i]) * fb[i];
@@ -203,8 +228,29 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       }
 #pragma unroll
       for (int i = 0; i < 7; ++i) {
-        gc[i] = Storage<S>::load(gA + (long long)i * N + cell);
+        gc[i] = ld_at(gzp, G7, colb, i * PB);
         sg += gc[i];
+      }
+      const bool wall_plane = a.zwall && (zp == 0 || zp == nz - 1);
+      const int zin = zp == 0 ? 1 : nz - 2;
+      const int wk = zp == 0 ? 0 : 1;
+      if (wall_plane) {
+        // eqs. (35)-(36): g_b = w T_b + g(x_f) - w T(x_f), on deviations
+        const S* gin = gA + PS * 7 * zin;
+        C gf[7], sfg = C(0);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+          gf[i] = ld_at(gin, G7, colb, i * PB);
+          sfg += gf[i];
+        }
+        const C Tb = a.wall_Tw[wk] ? C(a.wall_Tw[wk][col]) : a.wall_T[wk];
+        const C d = Tb - ph.T_ref - sfg;
+        sg = C(0);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+          gc[i] = gf[i] + (i == 0 ? ph.w0 : ph.w1) * d;
+          sg += gc[i];
+        }
       }
       rho_c = ph.rho_ref + sf;
       const C T = ph.T_ref + sg;
@@ -216,11 +262,10 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       s_ueq[s2][1][e_own] = jy / rho_c;
       s_ueq[s2][2][e_own] = jz / rho_c;
       if (has_halo) {
-        const long long hc = hcol + PS * zp;
         C hs = C(0), hx = C(0), hy = C(0), hz = C(0), hg = C(0);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-          const C v = Storage<S>::load(fA + (long long)i * N + hc);
+          const C v = ld_at(fz, F19, hcolb, i * PB);
           hs += v;
           if (CX[i]) hx += C(CX[i]) * v;
           if (CY[i]) hy += C(CY[i]) * v;
@@ -229,8 +274,25 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         C gv[7];
 #pragma unroll
         for (int i = 0; i < 7; ++i) {
-          gv[i] = Storage<S>::load(gA + (long long)i * N + hc);
+          gv[i] = ld_at(gzp, G7, hcolb, i * PB);
           hg += gv[i];
+        }
+        if (wall_plane) {
+          const S* gin = gA + PS * 7 * zin;
+          C gf[7], sfg = C(0);
+#pragma unroll
+          for (int i = 0; i < 7; ++i) {
+            gf[i] = ld_at(gin, G7, hcolb, i * PB);
+            sfg += gf[i];
+          }
+          const C Tb = a.wall_Tw[wk] ? C(a.wall_Tw[wk][hcol]) : a.wall_T[wk];
+          const C d = Tb - ph.T_ref - sfg;
+          hg = C(0);
+#pragma unroll
+          for (int i = 0; i < 7; ++i) {
+            gv[i] = gf[i] + (i == 0 ? ph.w0 : ph.w1) * d;
+            hg += gv[i];
+          }
         }
         const C hr = ph.rho_ref + hs;
         const C hT = ph.T_ref + hg;
@@ -294,16 +356,16 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           collide19(fa, rho, rho - ph.rho_ref, uex, uey, uez, dux, duy, duz, ph);
 #pragma unroll
           for (int i = 0; i < 19; ++i) {
-            const int xd = wrapn(x + CX[i], nx), yd = wrapn(y + CY[i], ny);
+            const unsigned db = (unsigned)(wrapn(x + CX[i], nx) + nx * wrapn(y + CY[i], ny)) * ES;
             int zd = zq + CZ[i];
             if (zd < 0 || zd >= nz) {
               if (a.zwall) {
-                Storage<S>::store(fB + (long long)opp19(i) * N + col + PS * zq, fa[i]);
+                st_at(fB + PS * 19 * zq, F19, colb, opp19(i) * PB, fa[i]);
                 continue;
               }
               zd = wrapn(zd, nz);
             }
-            Storage<S>::store(fB + (long long)i * N + xd + (long long)nx * yd + PS * zd, fa[i]);
+            st_at(fB + PS * 19 * zd, F19, db, i * PB, fa[i]);
           }
         }
       }
@@ -339,7 +401,6 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     const C og1 = ga[1], og2 = ga[2], og3 = ga[3], og4 = ga[4], og6 = ga[6];
     const bool do_g = r_exists && r >= z0 && r < z1;
     if (do_g) {
-      const long long cell = col + PS * zr;
       const C T = ph.T_ref + (ga[0] + ga[1] + ga[2] + ga[3] + ga[4] + ga[5] + ga[6]);
       C gx, gy, gz;
       local_gradT(ga, ph, gx, gy, gz);
@@ -347,7 +408,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       const C Fbar = rho * ph.cv * (ua[0] * gx + ua[1] * gy + ua[2] * gz) + T * pr_dpdT(rho, T, ph) * d0;
       const C og0 = ga[0];
       collide7(ga, Fbar, ph);
-      Storage<S>::store(gB + cell, og0 + (ga[0] - og0) * (inv_cv / rho));
+      st_at(gB + PS * 7 * zr, G7, colb, 0u, og0 + (ga[0] - og0) * (inv_cv / rho));
       // +z: destination is plane r+1 of this column (old value in gb)
       {
         int zd = zr + 1;
@@ -356,7 +417,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           if (a.zwall) ok = false; else zd = 0;
         }
         if (ok)
-          Storage<S>::store(gB + 5 * N + col + PS * zd, gb[5] + (ga[5] - gb[5]) * (inv_cv / rho_b));
+          st_at(gB + PS * 7 * zd, G7, colb, 5 * PB, gb[5] + (ga[5] - gb[5]) * (inv_cv / rho_b));
       }
       // -z: destination is plane r-1 of this column (old value kept from last iteration)
       {
@@ -366,7 +427,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           if (a.zwall) ok = false; else zd = nz - 1;
         }
         if (ok)
-          Storage<S>::store(gB + 6 * N + col + PS * zd, g6_old + (ga[6] - g6_old) * (inv_cv / pend_rho));
+          st_at(gB + PS * 7 * zd, G7, colb, 6 * PB, g6_old + (ga[6] - g6_old) * (inv_cv / pend_rho));
       }
       const int rs = (k + 2) & 3;  // rho / ring slot of plane r
 #pragma unroll
@@ -378,8 +439,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           const int slot = i == 1 ? ty : (i == 2 ? TY + ty : (i == 3 ? 2 * TY + tx : 2 * TY + TX + tx));
           const C gold = s_gr[rs][slot];
           const C rd = s_rho[rs][e_own + CX[i] + CY[i] * EX];
-          const long long dcell = wrapn(x + CX[i], nx) + (long long)nx * wrapn(y + CY[i], ny) + PS * zr;
-          Storage<S>::store(gB + (long long)i * N + dcell, gold + (ga[i] - gold) * (inv_cv / rd));
+          const unsigned db = (unsigned)(wrapn(x + CX[i], nx) + nx * wrapn(y + CY[i], ny)) * ES;
+          st_at(gB + PS * 7 * zr, G7, db, i * PB, gold + (ga[i] - gold) * (inv_cv / rd));
         }
       }
     }
@@ -412,9 +473,15 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   finish_pulls();
 }
 
+// Tile height: 16 rows (1024 threads, 1.33x halo reads) for 32-bit and
+// 16-bit storage; 8 rows for FP64, whose LDS rings need twice the space.
+// LBM_FUSED_TY=8 or 16 overrides the choice for 32- and 16-bit storage.
 inline int fused_tile_height(int precision) {
-  (void)precision;
-  return 8;
+  if (precision == LBM_FP64) return 8;
+  if (const char* ev = std::getenv("LBM_FUSED_TY")) {
+    if (std::atoi(ev) == 8) return 8;
+  }
+  return 16;
 }
 
 inline bool fused_supported(const lbm_params& p) {
@@ -434,7 +501,7 @@ template <typename S>
 struct FusedImpl {
   using C = typename Storage<S>::C;
   static hipError_t step(const lbm_params& p, const Phys<C>& ph, hipStream_t stream, const S* fA, const S* gA, S* fB,
-                         S* gB, int* flag, int chunk_planes) {
+                         S* gB, const double* Tw0, const double* Tw1, int* flag, int chunk_planes) {
     FusedArgs<C> a;
     a.ph = ph;
     a.nx = p.nx;
@@ -442,13 +509,24 @@ struct FusedImpl {
     a.nz = p.nz;
     a.N = (long long)p.nx * p.ny * p.nz;
     a.zwall = p.face[4] == LBM_FACE_WALL;
-    constexpr int TY = 8;
+    const int TY = fused_tile_height(p.precision);
     a.tiles_x = p.nx / FTX;
     a.ntiles = a.tiles_x * (p.ny / TY);
     a.chunk = chunk_planes > 0 ? chunk_planes : p.nz;
     const int nchunks = (p.nz + a.chunk - 1) / a.chunk;
+    a.wall_T[0] = (C)p.face_T[4];
+    a.wall_T[1] = (C)p.face_T[5];
+    a.wall_Tw[0] = Tw0;
+    a.wall_Tw[1] = Tw1;
     a.flag = flag;
-    hipLaunchKernelGGL((k_fused<S, TY>), dim3(a.ntiles * nchunks), dim3(FTX * TY), 0, stream, fA, gA, fB, gB, a);
+    if constexpr (sizeof(S) <= 4) {
+      if (TY == 16) {
+        hipLaunchKernelGGL((k_fused<S, 16>), dim3(a.ntiles * nchunks), dim3(FTX * 16), 0, stream, fA, gA, fB, gB,
+                           a);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((k_fused<S, 8>), dim3(a.ntiles * nchunks), dim3(FTX * 8), 0, stream, fA, gA, fB, gB, a);
     return hipGetLastError();
   }
 };

@@ -22,6 +22,13 @@ struct Geom {
   long long N;
 };
 
+// Device layout of the populations: plane-major structure of arrays.
+// Population i of cell (x, y, z) of a Q-velocity lattice is element
+// (z*Q + i)*nx*ny + x + nx*y, so one plane of one direction is contiguous.
+__device__ __forceinline__ long long pidx(const Geom& g, int Q, int i, int x, int y, int z) {
+  return ((long long)z * Q + i) * ((long long)g.nx * g.ny) + x + (long long)g.nx * y;
+}
+
 template <typename C>
 struct Faces {
   C face_T[6];
@@ -162,13 +169,11 @@ __global__ void __launch_bounds__(256) k_thermal_dirichlet(S* __restrict__ gpop,
   else { x = u; y = v; z = fixed; }
   const Node n = classify(g, x, y, z);
   if (n.prio != k) return;  // handled by the launch slice of its priority face
-  const long long cb = cell_index(g, x, y, z);
-  const long long cf = cell_index(g, x + n.ix, y + n.iy, z + n.iz);
   C gf[7];
   C sum = C(0);
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
-    gf[i] = Storage<S>::load(gpop + (long long)i * g.N + cf);
+    gf[i] = Storage<S>::load(gpop + pidx(g, 7, i, x + n.ix, y + n.iy, z + n.iz));
     sum += gf[i];
   }
   const C Tb = boundary_T(g, fc, n.prio, x, y);
@@ -176,7 +181,7 @@ __global__ void __launch_bounds__(256) k_thermal_dirichlet(S* __restrict__ gpop,
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
     const C w = i == 0 ? ph.w0 : ph.w1;
-    Storage<S>::store(gpop + (long long)i * g.N + cb, gf[i] + w * d);
+    Storage<S>::store(gpop + pidx(g, 7, i, x, y, z), gf[i] + w * d);
   }
 }
 
@@ -196,9 +201,9 @@ __global__ void __launch_bounds__(256) k_macro(const S* __restrict__ fpop, const
   const int z = (int)(c / ((long long)g.nx * g.ny));
   C sf = C(0), sg = C(0);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) sf += Storage<S>::load(fpop + (long long)i * g.N + c);
+  for (int i = 0; i < 19; ++i) sf += Storage<S>::load(fpop + pidx(g, 19, i, x, y, z));
 #pragma unroll
-  for (int i = 0; i < 7; ++i) sg += Storage<S>::load(gpop + (long long)i * g.N + c);
+  for (int i = 0; i < 7; ++i) sg += Storage<S>::load(gpop + pidx(g, 7, i, x, y, z));
   C rho = ph.rho_ref + sf;
   const Node n = classify(g, x, y, z);
   if (n.pressure) rho = fc.face_rho[n.prio];
@@ -280,7 +285,7 @@ __global__ void __launch_bounds__(256) k_force(S* __restrict__ fpop, const typen
   const C rho = rho_f[c];
   C f[19];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) f[i] = Storage<S>::load(fpop + (long long)i * g.N + c);
+  for (int i = 0; i < 19; ++i) f[i] = Storage<S>::load(fpop + pidx(g, 19, i, x, y, z));
   const Node n = classify(g, x, y, z);
   if (n.pressure) {
     const C rout = fc.face_rho[n.prio];
@@ -289,12 +294,11 @@ __global__ void __launch_bounds__(256) k_force(S* __restrict__ fpop, const typen
     } else {
       // edge / corner of pressure faces: non-equilibrium extrapolation of
       // every population from the inward diagonal neighbour x_f
-      const long long cf = cell_index(g, x + n.ix, y + n.iy, z + n.iz);
       C ff[19];
       C sfr = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
-        ff[i] = Storage<S>::load(fpop + (long long)i * g.N + cf);
+        ff[i] = Storage<S>::load(fpop + pidx(g, 19, i, x + n.ix, y + n.iy, z + n.iz));
         sfr += ff[i];
         jx += C(CX[i]) * ff[i];
         jy += C(CY[i]) * ff[i];
@@ -311,7 +315,7 @@ __global__ void __launch_bounds__(256) k_force(S* __restrict__ fpop, const typen
       }
     }
 #pragma unroll
-    for (int i = 0; i < 19; ++i) Storage<S>::store(fpop + (long long)i * g.N + c, f[i]);
+    for (int i = 0; i < 19; ++i) Storage<S>::store(fpop + pidx(g, 19, i, x, y, z), f[i]);
   }
   C jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
@@ -364,14 +368,14 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
   }
   C gp[7];
 #pragma unroll
-  for (int i = 0; i < 7; ++i) gp[i] = Storage<S>::load(gA + (long long)i * N + c);
+  for (int i = 0; i < 7; ++i) gp[i] = Storage<S>::load(gA + pidx(g, 7, i, x, y, z));
   C gx, gy, gz;
   local_gradT(gp, ph, gx, gy, gz);
   const C rux = ux + C(0.5) * dux, ruy = uy + C(0.5) * duy, ruz = uz + C(0.5) * duz;
   const C Fbar = rho * ph.cv * (rux * gx + ruy * gy + ruz * gz) + T * pr_dpdT(rho, T, ph) * div;
   C f[19];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) f[i] = Storage<S>::load(fA + (long long)i * N + c);
+  for (int i = 0; i < 19; ++i) f[i] = Storage<S>::load(fA + pidx(g, 19, i, x, y, z));
   collide19(f, rho, rho - ph.rho_ref, ux, uy, uz, dux, duy, duz, ph);
   collide7(gp, Fbar, ph);
   // push streaming, eq. (9); links leaving through a wall bounce back (eq. (34))
@@ -393,8 +397,8 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
         bounce = g.face[k] == FACE_WALL;
       }
     }
-    if (ok) Storage<S>::store(fB + (long long)i * N + cell_index(g, xd, yd, zd), f[i]);
-    else if (bounce) Storage<S>::store(fB + (long long)opp19(i) * N + c, f[i]);
+    if (ok) Storage<S>::store(fB + pidx(g, 19, i, xd, yd, zd), f[i]);
+    else if (bounce) Storage<S>::store(fB + pidx(g, 19, opp19(i), x, y, z), f[i]);
   }
   // D3Q7 push with the rho c_v blend of eq. (13), rho at the destination, time t
 #pragma unroll
@@ -412,9 +416,9 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
     }
     if (!ok) continue;
     const long long cd = cell_index(g, xd, yd, zd);
-    const C gold = Storage<S>::load(gA + (long long)i * N + cd);
+    const C gold = Storage<S>::load(gA + pidx(g, 7, i, xd, yd, zd));
     const C inv = C(1) / (rho_f[cd] * ph.cv);
-    Storage<S>::store(gB + (long long)i * N + cd, gold + (gp[i] - gold) * inv);
+    Storage<S>::store(gB + pidx(g, 7, i, xd, yd, zd), gold + (gp[i] - gold) * inv);
   }
 }
 
@@ -424,20 +428,23 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_init(S* __restrict__ fpop, S* __restrict__ gpop,
                                               const double* __restrict__ rho, const double* __restrict__ u,
                                               const double* __restrict__ T, long long c0, long long len,
-                                              long long N, double rho_ref, double T_ref, double w0, double w1) {
+                                              long long N, int nz, double rho_ref, double T_ref, double w0,
+                                              double w1) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= len) return;
   const long long c = c0 + t;
+  const long long PS = N / nz;
+  const long long zc = c / PS, xy = c - zc * PS;
   const double r = rho[t];
   const double vx = u ? u[t] : 0.0, vy = u ? u[t + len] : 0.0, vz = u ? u[t + 2 * len] : 0.0;
 #pragma unroll
   for (int i = 0; i < 19; ++i)
-    Storage<S>::store(fpop + (long long)i * N + c,
+    Storage<S>::store(fpop + (zc * 19 + i) * PS + xy,
                       (typename Storage<S>::C)feq19_dev<double>(i, r, rho_ref, vx, vy, vz));
   const double dT = T[t] - T_ref;
 #pragma unroll
   for (int i = 0; i < 7; ++i)
-    Storage<S>::store(gpop + (long long)i * N + c, (typename Storage<S>::C)((i == 0 ? w0 : w1) * dT));
+    Storage<S>::store(gpop + (zc * 7 + i) * PS + xy, (typename Storage<S>::C)((i == 0 ? w0 : w1) * dT));
 }
 
 template <typename C>
@@ -461,20 +468,22 @@ __global__ void __launch_bounds__(256) k_fields_out(const C* __restrict__ rho, c
 template <typename S>
 __global__ void __launch_bounds__(256) k_pops_out(const S* __restrict__ fpop, const S* __restrict__ gpop,
                                                   double* __restrict__ of, double* __restrict__ og,
-                                                  long long c0, long long len, long long N, double rho_ref,
-                                                  double T_ref, double w0, double w1) {
+                                                  long long c0, long long len, long long N, int nz,
+                                                  double rho_ref, double T_ref, double w0, double w1) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= len) return;
   const long long c = c0 + t;
+  const long long PS = N / nz;
+  const long long zc = c / PS, xy = c - zc * PS;
   if (of) {
 #pragma unroll
     for (int i = 0; i < 19; ++i)
-      of[t + i * len] = (double)Storage<S>::load(fpop + (long long)i * N + c) + w19<double>(i) * rho_ref;
+      of[t + i * len] = (double)Storage<S>::load(fpop + (zc * 19 + i) * PS + xy) + w19<double>(i) * rho_ref;
   }
   if (og) {
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-      og[t + i * len] = (double)Storage<S>::load(gpop + (long long)i * N + c) + (i == 0 ? w0 : w1) * T_ref;
+      og[t + i * len] = (double)Storage<S>::load(gpop + (zc * 7 + i) * PS + xy) + (i == 0 ? w0 : w1) * T_ref;
   }
 }
 

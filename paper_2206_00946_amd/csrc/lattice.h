@@ -144,62 +144,44 @@ __device__ __forceinline__ void populations19(const C* m, C* f) {
   f[6] = C(0.5) * (Cz - dz);
 }
 
-// Velocity part q(rho, u) of the equilibrium moments of eq. (10): the
-// equilibrium moments are rho*e + q with e = moments of the rest weights
-// (1 at rows 0 and 4, 1/9 at rows 16-18, 0 elsewhere).
-template <typename C>
-__device__ __forceinline__ void meq_velocity_part(C rho, C ux, C uy, C uz, C* q) {
-  const C xx = ux * ux, yy = uy * uy, zz = uz * uz;
-  const C usq = xx + yy + zz;
-  const C third = C(1) / C(3);
-  const C r3 = rho * third;
-  q[0] = C(0);
-  q[1] = rho * ux;
-  q[2] = rho * uy;
-  q[3] = rho * uz;
-  q[4] = rho * usq;
-  q[5] = rho * (C(2) * xx - yy - zz);
-  q[6] = rho * (yy - zz);
-  q[7] = rho * ux * uy;
-  q[8] = rho * ux * uz;
-  q[9] = rho * uy * uz;
-  q[10] = r3 * uy;
-  q[11] = r3 * ux;
-  q[12] = r3 * uz;
-  q[13] = r3 * ux;
-  q[14] = r3 * uz;
-  q[15] = r3 * uy;
-  const C rest = -rho * usq / C(6);
-  q[16] = rest + r3 * (xx + yy);
-  q[17] = rest + r3 * (xx + zz);
-  q[18] = rest + r3 * (yy + zz);
-}
-
-template <typename C>
-__device__ __forceinline__ C rest_moment(int k) {
-  return (k == 0 || k == 4) ? C(1) : (k >= 16 ? C(1) / C(9) : C(0));
-}
-
-template <typename C>
-__device__ __forceinline__ C rate19(int k, const Phys<C>& ph) {
-  return k < 4 ? C(1) : (k == 4 ? ph.s_e : (k < 10 ? ph.s_nu : (k < 16 ? ph.s_q : ph.s_pi)));
-}
-
 // eq. (8): m* = m - L (m - meq(u_eq)) + [meq(u_eq + du) - meq(u_eq)], applied
 // to deviations: mt*_k = (1 - s_k)(mt_k - rt e_k - q_k(u_eq)) + rt e_k + q_k(u_eq + du),
-// rt = rho - rho_ref.  f is overwritten by the post-collision deviations.
+// rt = rho - rho_ref, where rho e + q(rho, u) are the equilibrium moments of
+// eq. (10) (e: moments of the rest weights, 1 at rows 0 and 4, 1/9 at rows
+// 16-18).  f is overwritten by the post-collision deviations.
 template <typename C>
 __device__ __forceinline__ void collide19(C* f, C rho, C rt, C ux, C uy, C uz, C dux, C duy,
                                           C duz, const Phys<C>& ph) {
-  C m[19], q0[19], q1[19];
+  C m[19];
   moments19(f, m);
-  meq_velocity_part(rho, ux, uy, uz, q0);
-  meq_velocity_part(rho, ux + dux, uy + duy, uz + duz, q1);
-#pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const C e = rt * rest_moment<C>(k);
-    m[k] = (C(1) - rate19(k, ph)) * (m[k] - e - q0[k]) + e + q1[k];
-  }
+  const C vx = ux + dux, vy = uy + duy, vz = uz + duz;
+  const C third = C(1) / C(3);
+  const C xx0 = ux * ux, yy0 = uy * uy, zz0 = uz * uz, s0 = xx0 + yy0 + zz0;
+  const C xx1 = vx * vx, yy1 = vy * vy, zz1 = vz * vz, s1 = xx1 + yy1 + zz1;
+  const C oe = C(1) - ph.s_e, on = C(1) - ph.s_nu, oq = C(1) - ph.s_q, op = C(1) - ph.s_pi;
+  // rows 0-3 relax with rate 1: density and momentum after forcing
+  m[0] = rt;
+  m[1] = rho * vx;
+  m[2] = rho * vy;
+  m[3] = rho * vz;
+  m[4] = oe * (m[4] - rt - rho * s0) + rt + rho * s1;
+  m[5] = on * (m[5] - rho * (C(2) * xx0 - yy0 - zz0)) + rho * (C(2) * xx1 - yy1 - zz1);
+  m[6] = on * (m[6] - rho * (yy0 - zz0)) + rho * (yy1 - zz1);
+  m[7] = on * (m[7] - rho * ux * uy) + rho * vx * vy;
+  m[8] = on * (m[8] - rho * ux * uz) + rho * vx * vz;
+  m[9] = on * (m[9] - rho * uy * uz) + rho * vy * vz;
+  const C r3 = rho * third;
+  m[10] = oq * (m[10] - r3 * uy) + r3 * vy;
+  m[11] = oq * (m[11] - r3 * ux) + r3 * vx;
+  m[12] = oq * (m[12] - r3 * uz) + r3 * vz;
+  m[13] = oq * (m[13] - r3 * ux) + r3 * vx;
+  m[14] = oq * (m[14] - r3 * uz) + r3 * vz;
+  m[15] = oq * (m[15] - r3 * uy) + r3 * vy;
+  const C e9 = rt / C(9);
+  const C rest0 = -rho * s0 / C(6), rest1 = -rho * s1 / C(6);
+  m[16] = op * (m[16] - e9 - rest0 - r3 * (xx0 + yy0)) + e9 + rest1 + r3 * (xx1 + yy1);
+  m[17] = op * (m[17] - e9 - rest0 - r3 * (xx0 + zz0)) + e9 + rest1 + r3 * (xx1 + zz1);
+  m[18] = op * (m[18] - e9 - rest0 - r3 * (yy0 + zz0)) + e9 + rest1 + r3 * (yy1 + zz1);
   populations19(m, f);
 }
 

@@ -243,13 +243,9 @@ struct Impl {
 
   static hipError_t step_fused(lbm_ctx* ctx) {
     const lbm_params& p = ctx->p;
-    if (p.face[4] == LBM_FACE_WALL) {
-      // Dirichlet temperatures of the wall nodes (eqs. (35)-(36)) before the single pass
-      hipError_t e = thermal_dirichlet(ctx, (S*)ctx->gA);
-      if (e != hipSuccess) return e;
-    }
     return FusedImpl<S>::step(p, phys_of<C>(p), ctx->stream, (const S*)ctx->fA, (const S*)ctx->gA, (S*)ctx->fB,
-                              (S*)ctx->gB, ctx->flag, ctx->fused_chunk);
+                              (S*)ctx->gB, ctx->has_Tw[0] ? ctx->Tw[0] : nullptr,
+                              ctx->has_Tw[1] ? ctx->Tw[1] : nullptr, ctx->flag, ctx->fused_chunk);
   }
 
   static hipError_t step(lbm_ctx* ctx) {
@@ -264,7 +260,7 @@ struct Impl {
                               long long len) {
     const lbm_params& p = ctx->p;
     hipLaunchKernelGGL(k_init<S>, dim3(blocks_for(len)), dim3(256), 0, ctx->stream, (S*)ctx->fA, (S*)ctx->gA, drho,
-                       du, dT, c0, len, ncells(p), p.rho_ref, p.T_ref, 1.0 - p.wbar, p.wbar / 6.0);
+                       du, dT, c0, len, ncells(p), p.nz, p.rho_ref, p.T_ref, 1.0 - p.wbar, p.wbar / 6.0);
     return hipGetLastError();
   }
 
@@ -279,7 +275,7 @@ struct Impl {
   static hipError_t pops_slab(lbm_ctx* ctx, double* of, double* og, long long c0, long long len) {
     const lbm_params& p = ctx->p;
     hipLaunchKernelGGL(k_pops_out<S>, dim3(blocks_for(len)), dim3(256), 0, ctx->stream, (const S*)ctx->fA,
-                       (const S*)ctx->gA, of, og, c0, len, ncells(p), p.rho_ref, p.T_ref, 1.0 - p.wbar,
+                       (const S*)ctx->gA, of, og, c0, len, ncells(p), p.nz, p.rho_ref, p.T_ref, 1.0 - p.wbar,
                        p.wbar / 6.0);
     return hipGetLastError();
   }

@@ -53,4 +53,61 @@ struct Storage<bf16> {
   }
 };
 
+// Raw buffer access: a descriptor over one uniform range (base, bytes) and a
+// per-lane byte offset.  Offsets outside the range read 0 and drop stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_range(const void* base, unsigned bytes) {
+  // word 3 of the descriptor for gfx9-family untyped 32-bit-format access
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename S>
+struct Buf;
+
+// voff: per-lane byte offset; soff: uniform byte offset (scalar operand)
+template <>
+struct Buf<double> {
+  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+  }
+};
+
+template <>
+struct Buf<float> {
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  }
+};
+
+template <>
+struct Buf<_Float16> {
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+  }
+  static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, static_cast<_Float16>(v)), r, voff,
+                                          soff, 0);
+  }
+};
+
+template <>
+struct Buf<bf16> {
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    bf16 h;
+    h.bits = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    return Storage<bf16>::load(&h);
+  }
+  static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+    bf16 h;
+    Storage<bf16>::store(&h, v);
+    __builtin_amdgcn_raw_buffer_store_b16(h.bits, r, voff, soff, 0);
+  }
+};
+
 }  // namespace lbm

@@ -275,6 +275,18 @@ def test_fused_parity(P, name, prec, chunk, monkeypatch):
 
 
 @pytest.mark.parametrize("name", list(FUSED))
+def test_fused_fp32_tile_height_8(P, name, monkeypatch):
+    """32-bit storage with the 8-row tile (the 16-row tile is the default)."""
+    monkeypatch.setenv("LBM_FUSED_TY", "8")
+    w = FUSED[name]()
+    ref = oracle_run(w, 20, record=(20,))
+    sim = P.from_workload(w, precision="fp32")
+    sim.step(20)
+    _compare(f"{name} fp32 ty=8 step 20", sim.fields(), ref[20], 1e-4, 2e-2, 1e-4)
+    sim.close()
+
+
+@pytest.mark.parametrize("name", list(FUSED))
 def test_fused_matches_unfused_fp64(P, name, monkeypatch):
     w = FUSED[name]()
     out = []
