@@ -155,8 +155,14 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   const unsigned colb = col * ES;
   const unsigned PB = (unsigned)(nx * ny) * ES;  // bytes of one plane of one direction
   const unsigned F19 = 19 * PB, G7 = 7 * PB;       // bytes of all directions of one plane
+  // byte offsets from this column to its periodic x / y neighbours in a plane
+  const int dxm = (wrapn(x - 1, nx) - x) * (int)ES, dxp = (wrapn(x + 1, nx) - x) * (int)ES;
+  const int dym = (wrapn(y - 1, ny) - y) * nx * (int)ES, dyp = (wrapn(y + 1, ny) - y) * nx * (int)ES;
+  auto nb_off = [&](int cx, int cy) -> unsigned {
+    return colb + (unsigned)((cx < 0 ? dxm : (cx > 0 ? dxp : 0)) + (cy < 0 ? dym : (cy > 0 ? dyp : 0)));
+  };
   const int e_own = TL::interior_e(tx, ty);
-  const C inv_cv = C(1) / ph.cv;
+  const C inv_cv = rcp(ph.cv);
 
   // helper cells of this thread
   int hex, hey;
@@ -203,104 +209,130 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       const int sx = tx - CX[i], sy = ty - CY[i];
       if (sx < 0 || sx >= TX || sy < 0 || sy >= TY) continue;
       const C gs = s_gs[i - 1][sy * TX + sx];
-      st_at(gz, G7, colb, i * PB, pend_g[i - 1] + (gs - pend_g[i - 1]) * (inv_cv / pend_rho));
+      st_at(gz, G7, colb, i * PB, pend_g[i - 1] + (gs - pend_g[i - 1]) * (inv_cv * rcp(pend_rho)));
     }
   };
 
+  // register prefetch of the next plane's populations (tile and halo cell);
+  // with 16 rows or FP64 the registers are not there and planes load in place
+  constexpr bool PF = TY <= 8 && sizeof(C) == 4;
+  C pfi[26], pfh[26];
+  auto load_cell = [&](int zn, unsigned off, C* l) {
+    const S* fz = fA + PS * 19 * zn;
+    const S* gz = gA + PS * 7 * zn;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) l[i] = ld_at(fz, F19, off, i * PB);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) l[19 + i] = ld_at(gz, G7, off, i * PB);
+  };
+  auto prefetch = [&](int zn) {
+    load_cell(zn, colb, pfi);
+    if (has_halo) load_cell(zn, hcolb, pfh);
+  };
+#pragma unroll
+  for (int i = 0; i < 26; ++i) pfi[i] = pfh[i] = C(0);
+
   const int p_begin = z0 - 2, p_end = z1 + 1;
+  if constexpr (PF) {
+    int zf;
+    if (plane_of(p_begin, zf)) prefetch(zf);
+  }
   for (int p = p_begin; p <= p_end; ++p) {
     const int k = p - p_begin;
     const int s3 = k % 3, s4 = k & 3, s2 = k & 1;
     int zp;
     const bool exists = plane_of(p, zp);
-    // ---------------------------------------------------------------- load plane p
+    // ---------------------------------------------------------------- plane p: take the prefetched values
+    C hv[19], gv[7];
     if (exists) {
-      const S* fz = fA + PS * 19 * zp;
-      const S* gzp = gA + PS * 7 * zp;
+      C li[26];
+      if constexpr (!PF) load_cell(zp, colb, li);
+      const C* vi = PF ? pfi : li;
+#pragma unroll
+      for (int i = 0; i < 19; ++i) fb[i] = vi[i];
+#pragma unroll
+      for (int i = 0; i < 7; ++i) gc[i] = vi[19 + i];
+      if constexpr (PF) {
+        if (has_halo) {
+#pragma unroll
+          for (int i = 0; i < 19; ++i) hv[i] = pfh[i];
+#pragma unroll
+          for (int i = 0; i < 7; ++i) gv[i] = pfh[19 + i];
+        }
+      }
+    }
+    // issue the loads of plane p+1; they complete while plane p-1 and p-2 are updated
+    if constexpr (PF) {
+      int zn;
+      if (p < p_end && plane_of(p + 1, zn)) prefetch(zn);
+    }
+    if (exists) {
+      const bool wall_plane = a.zwall && (zp == 0 || zp == nz - 1);
+      const int zin = zp == 0 ? 1 : nz - 2;
+      const int wk = zp == 0 ? 0 : 1;
+      // eqs. (35)-(36) on a wall plane: g_b = w T_b + g(x_f) - w T(x_f), on deviations
+      auto dirichlet = [&](C* g7, unsigned off, unsigned fcol) {
+        const S* gin = gA + PS * 7 * zin;
+        C gf[7], sfg = C(0);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+          gf[i] = ld_at(gin, G7, off, i * PB);
+          sfg += gf[i];
+        }
+        const C Tb = a.wall_Tw[wk] ? C(a.wall_Tw[wk][fcol]) : a.wall_T[wk];
+        const C d = Tb - ph.T_ref - sfg;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) g7[i] = gf[i] + (i == 0 ? ph.w0 : ph.w1) * d;
+      };
+      if (wall_plane) dirichlet(gc, colb, col);
       C sf = C(0), jx = C(0), jy = C(0), jz = C(0), sg = C(0);
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
-        fb[i] = ld_at(fz, F19, colb, i * PB);
         sf += fb[i];
         if (CX[i]) jx += C(CX[i]) * fb[i];
         if (CY[i]) jy += C(CY[i]) * fb[i];
         if (CZ[i]) jz += C(CZ[i]) * fb[i];
       }
 #pragma unroll
-      for (int i = 0; i < 7; ++i) {
-        gc[i] = ld_at(gzp, G7, colb, i * PB);
-        sg += gc[i];
-      }
-      const bool wall_plane = a.zwall && (zp == 0 || zp == nz - 1);
-      const int zin = zp == 0 ? 1 : nz - 2;
-      const int wk = zp == 0 ? 0 : 1;
-      if (wall_plane) {
-        // eqs. (35)-(36): g_b = w T_b + g(x_f) - w T(x_f), on deviations
-        const S* gin = gA + PS * 7 * zin;
-        C gf[7], sfg = C(0);
-#pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          gf[i] = ld_at(gin, G7, colb, i * PB);
-          sfg += gf[i];
-        }
-        const C Tb = a.wall_Tw[wk] ? C(a.wall_Tw[wk][col]) : a.wall_T[wk];
-        const C d = Tb - ph.T_ref - sfg;
-        sg = C(0);
-#pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          gc[i] = gf[i] + (i == 0 ? ph.w0 : ph.w1) * d;
-          sg += gc[i];
-        }
-      }
+      for (int i = 0; i < 7; ++i) sg += gc[i];
       rho_c = ph.rho_ref + sf;
       const C T = ph.T_ref + sg;
       const C rad = psi_radicand(rho_c, T, ph);
       if (nonphysical(rho_c, T, rad, ph)) a.flag[0] = 1;
-      s_psi[s3][e_own] = sqrt(rad);
+      s_psi[s3][e_own] = fsqrt(rad);
       s_rho[s4][e_own] = rho_c;
-      s_ueq[s2][0][e_own] = jx / rho_c;
-      s_ueq[s2][1][e_own] = jy / rho_c;
-      s_ueq[s2][2][e_own] = jz / rho_c;
+      const C ir = rcp(rho_c);
+      s_ueq[s2][0][e_own] = jx * ir;
+      s_ueq[s2][1][e_own] = jy * ir;
+      s_ueq[s2][2][e_own] = jz * ir;
       if (has_halo) {
+        if constexpr (!PF) {
+          C lh[26];
+          load_cell(zp, hcolb, lh);
+#pragma unroll
+          for (int i = 0; i < 19; ++i) hv[i] = lh[i];
+#pragma unroll
+          for (int i = 0; i < 7; ++i) gv[i] = lh[19 + i];
+        }
+        if (wall_plane) dirichlet(gv, hcolb, hcol);
         C hs = C(0), hx = C(0), hy = C(0), hz = C(0), hg = C(0);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-          const C v = ld_at(fz, F19, hcolb, i * PB);
-          hs += v;
-          if (CX[i]) hx += C(CX[i]) * v;
-          if (CY[i]) hy += C(CY[i]) * v;
-          if (CZ[i]) hz += C(CZ[i]) * v;
+          hs += hv[i];
+          if (CX[i]) hx += C(CX[i]) * hv[i];
+          if (CY[i]) hy += C(CY[i]) * hv[i];
+          if (CZ[i]) hz += C(CZ[i]) * hv[i];
         }
-        C gv[7];
 #pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          gv[i] = ld_at(gzp, G7, hcolb, i * PB);
-          hg += gv[i];
-        }
-        if (wall_plane) {
-          const S* gin = gA + PS * 7 * zin;
-          C gf[7], sfg = C(0);
-#pragma unroll
-          for (int i = 0; i < 7; ++i) {
-            gf[i] = ld_at(gin, G7, hcolb, i * PB);
-            sfg += gf[i];
-          }
-          const C Tb = a.wall_Tw[wk] ? C(a.wall_Tw[wk][hcol]) : a.wall_T[wk];
-          const C d = Tb - ph.T_ref - sfg;
-          hg = C(0);
-#pragma unroll
-          for (int i = 0; i < 7; ++i) {
-            gv[i] = gf[i] + (i == 0 ? ph.w0 : ph.w1) * d;
-            hg += gv[i];
-          }
-        }
+        for (int i = 0; i < 7; ++i) hg += gv[i];
         const C hr = ph.rho_ref + hs;
         const C hT = ph.T_ref + hg;
-        s_psi[s3][he] = sqrt(psi_radicand(hr, hT, ph));
+        s_psi[s3][he] = fsqrt(psi_radicand(hr, hT, ph));
         s_rho[s4][he] = hr;
-        s_ueq[s2][0][he] = hx / hr;
-        s_ueq[s2][1][he] = hy / hr;
-        s_ueq[s2][2][he] = hz / hr;
+        const C ihr = rcp(hr);
+        s_ueq[s2][0][he] = hx * ihr;
+        s_ueq[s2][1][he] = hy * ihr;
+        s_ueq[s2][2][he] = hz * ihr;
         if (ridx >= 0) s_gr[s4][ridx] = gv[rdir];
       }
     }
@@ -339,7 +371,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         C Fx, Fy, Fz;
         force_at(e_own, Fx, Fy, Fz);
         const C rho = rho_b;
-        const C dux = Fx / rho, duy = Fy / rho, duz = Fz / rho;
+        const C irho = rcp(rho);
+        const C dux = Fx * irho, duy = Fy * irho, duz = Fz * irho;
         C uex = s_ueq[sq][0][e_own], uey = s_ueq[sq][1][e_own], uez = s_ueq[sq][2][e_own];
         if (wall_plane) {
           uex = -C(0.5) * dux;
@@ -354,28 +387,33 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         s_u[2][e_own] = ub[2];
         if (q >= z0 && q < z1) {
           collide19(fa, rho, rho - ph.rho_ref, uex, uey, uez, dux, duy, duz, ph);
+          // destination planes q-1, q, q+1 (periodic wrap); at a wall the
+          // links leaving the domain bounce back onto the opposite slot
+          const bool lo_out = zq == 0, hi_out = zq == nz - 1;
+          S* pm = fB + PS * 19 * (lo_out ? nz - 1 : zq - 1);
+          S* p0 = fB + PS * 19 * zq;
+          S* pp = fB + PS * 19 * (hi_out ? 0 : zq + 1);
+          if (!(a.zwall && (lo_out || hi_out))) {
 #pragma unroll
-          for (int i = 0; i < 19; ++i) {
-            const unsigned db = (unsigned)(wrapn(x + CX[i], nx) + nx * wrapn(y + CY[i], ny)) * ES;
-            int zd = zq + CZ[i];
-            if (zd < 0 || zd >= nz) {
-              if (a.zwall) {
-                st_at(fB + PS * 19 * zq, F19, colb, opp19(i) * PB, fa[i]);
-                continue;
-              }
-              zd = wrapn(zd, nz);
+            for (int i = 0; i < 19; ++i)
+              st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+              const bool out = (CZ[i] < 0 && lo_out) || (CZ[i] > 0 && hi_out);
+              if (out) st_at(p0, F19, colb, opp19(i) * PB, fa[i]);
+              else st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
             }
-            st_at(fB + PS * 19 * zd, F19, db, i * PB, fa[i]);
           }
         }
       }
       if (has_ring) {
         C Fx, Fy, Fz;
         force_at(re, Fx, Fy, Fz);
-        const C rho = s_rho[rq][re];
-        C vx = s_ueq[sq][0][re] + C(0.5) * Fx / rho;
-        C vy = s_ueq[sq][1][re] + C(0.5) * Fy / rho;
-        C vz = s_ueq[sq][2][re] + C(0.5) * Fz / rho;
+        const C hir = C(0.5) * rcp(s_rho[rq][re]);
+        C vx = s_ueq[sq][0][re] + Fx * hir;
+        C vy = s_ueq[sq][1][re] + Fy * hir;
+        C vz = s_ueq[sq][2][re] + Fz * hir;
         if (wall_plane) vx = vy = vz = C(0);
         s_u[0][re] = vx;
         s_u[1][re] = vy;
@@ -408,7 +446,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       const C Fbar = rho * ph.cv * (ua[0] * gx + ua[1] * gy + ua[2] * gz) + T * pr_dpdT(rho, T, ph) * d0;
       const C og0 = ga[0];
       collide7(ga, Fbar, ph);
-      st_at(gB + PS * 7 * zr, G7, colb, 0u, og0 + (ga[0] - og0) * (inv_cv / rho));
+      st_at(gB + PS * 7 * zr, G7, colb, 0u, og0 + (ga[0] - og0) * (inv_cv * rcp(rho)));
       // +z: destination is plane r+1 of this column (old value in gb)
       {
         int zd = zr + 1;
@@ -417,7 +455,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           if (a.zwall) ok = false; else zd = 0;
         }
         if (ok)
-          st_at(gB + PS * 7 * zd, G7, colb, 5 * PB, gb[5] + (ga[5] - gb[5]) * (inv_cv / rho_b));
+          st_at(gB + PS * 7 * zd, G7, colb, 5 * PB, gb[5] + (ga[5] - gb[5]) * (inv_cv * rcp(rho_b)));
       }
       // -z: destination is plane r-1 of this column (old value kept from last iteration)
       {
@@ -427,7 +465,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           if (a.zwall) ok = false; else zd = nz - 1;
         }
         if (ok)
-          st_at(gB + PS * 7 * zd, G7, colb, 6 * PB, g6_old + (ga[6] - g6_old) * (inv_cv / pend_rho));
+          st_at(gB + PS * 7 * zd, G7, colb, 6 * PB, g6_old + (ga[6] - g6_old) * (inv_cv * rcp(pend_rho)));
       }
       const int rs = (k + 2) & 3;  // rho / ring slot of plane r
 #pragma unroll
@@ -439,8 +477,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           const int slot = i == 1 ? ty : (i == 2 ? TY + ty : (i == 3 ? 2 * TY + tx : 2 * TY + TX + tx));
           const C gold = s_gr[rs][slot];
           const C rd = s_rho[rs][e_own + CX[i] + CY[i] * EX];
-          const unsigned db = (unsigned)(wrapn(x + CX[i], nx) + nx * wrapn(y + CY[i], ny)) * ES;
-          st_at(gB + PS * 7 * zr, G7, db, i * PB, gold + (ga[i] - gold) * (inv_cv / rd));
+          const unsigned db = nb_off(CX[i], CY[i]);
+          st_at(gB + PS * 7 * zr, G7, db, i * PB, gold + (ga[i] - gold) * (inv_cv * rcp(rd)));
         }
       }
     }
@@ -473,15 +511,16 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   finish_pulls();
 }
 
-// Tile height: 16 rows (1024 threads, 1.33x halo reads) for 32-bit and
-// 16-bit storage; 8 rows for FP64, whose LDS rings need twice the space.
-// LBM_FUSED_TY=8 or 16 overrides the choice for 32- and 16-bit storage.
+// Tile height: 8 rows (512 threads, one workgroup of 8 waves per compute
+// unit with room for the prefetch registers).  LBM_FUSED_TY=16 selects
+// 16-row tiles (fewer halo reads, 128-register limit) for 32- and 16-bit
+// storage; FP64 always uses 8 rows (its LDS rings need twice the space).
 inline int fused_tile_height(int precision) {
   if (precision == LBM_FP64) return 8;
   if (const char* ev = std::getenv("LBM_FUSED_TY")) {
-    if (std::atoi(ev) == 8) return 8;
+    if (std::atoi(ev) == 16) return 16;
   }
-  return 16;
+  return 8;
 }
 
 inline bool fused_supported(const lbm_params& p) {

@@ -39,33 +39,48 @@ struct Phys {
   C inv_b;
 };
 
+// ---------------------------------------------------------------- arithmetic
+// FP32 uses the hardware reciprocal and square root (about 1 ulp); FP64 keeps
+// correctly rounded division and square root.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double div(double a, double b) { return a / b; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+// division by a small integer constant: a multiplication for FP32
+template <int K>
+__device__ __forceinline__ float cdiv(float x) { return x * (1.0f / K); }
+template <int K>
+__device__ __forceinline__ double cdiv(double x) { return x / K; }
+
 // ---------------------------------------------------------------- EOS
 template <typename C>
 __device__ __forceinline__ C pr_xi_sq_root(C T, const Phys<C>& ph) {
   // 1 + kappa (1 - sqrt(T/Tc)), whose square is xi(T)
-  return C(1) + ph.kpr * (C(1) - sqrt(T / ph.Tc));
+  return C(1) + ph.kpr * (C(1) - fsqrt(div(T, ph.Tc)));
 }
 
 template <typename C>
 __device__ __forceinline__ C pr_pressure(C rho, C T, const Phys<C>& ph) {
   const C s = pr_xi_sq_root(T, ph);
   const C br = ph.b * rho;
-  return rho * ph.R * T / (C(1) - br) - ph.a * (s * s) * rho * rho / (C(1) + C(2) * br - br * br);
+  return div(rho * ph.R * T, C(1) - br) - div(ph.a * (s * s) * rho * rho, C(1) + C(2) * br - br * br);
 }
 
 // (d p / d T) at constant rho
 template <typename C>
 __device__ __forceinline__ C pr_dpdT(C rho, C T, const Phys<C>& ph) {
   const C s = pr_xi_sq_root(T, ph);
-  const C dxi = -ph.kpr * s / sqrt(T * ph.Tc);
+  const C dxi = div(-ph.kpr * s, fsqrt(T * ph.Tc));
   const C br = ph.b * rho;
-  return rho * ph.R / (C(1) - br) - ph.a * dxi * rho * rho / (C(1) + C(2) * br - br * br);
+  return div(rho * ph.R, C(1) - br) - div(ph.a * dxi * rho * rho, C(1) + C(2) * br - br * br);
 }
 
 // radicand of eq. (7): 2 (p - rho c_s^2) / G with c_s^2 = 1/3
 template <typename C>
 __device__ __forceinline__ C psi_radicand(C rho, C T, const Phys<C>& ph) {
-  return C(2) * (pr_pressure(rho, T, ph) - rho / C(3)) / ph.G;
+  return div(C(2) * (pr_pressure(rho, T, ph) - cdiv<3>(rho)), ph.G);
 }
 
 template <typename C>
@@ -129,7 +144,7 @@ __device__ __forceinline__ void populations19(const C* m, C* f) {
   const C S = m[4] - C(2) * (m[16] + m[17] + m[18]);      // sum of the six axis populations
   const C P = m[5] - m[16] - m[17] + C(2) * m[18];         // 2A - B - C
   const C Q = m[6] - m[16] + m[17];                         // B - C
-  const C A = (S + P) / C(3);
+  const C A = cdiv<3>(S + P);
   const C B = C(0.5) * (S - A + Q);
   const C Cz = C(0.5) * (S - A - Q);
   const C dx = m[1] - m[11] - m[13];
@@ -177,8 +192,8 @@ __device__ __forceinline__ void collide19(C* f, C rho, C rt, C ux, C uy, C uz, C
   m[13] = oq * (m[13] - r3 * ux) + r3 * vx;
   m[14] = oq * (m[14] - r3 * uz) + r3 * vz;
   m[15] = oq * (m[15] - r3 * uy) + r3 * vy;
-  const C e9 = rt / C(9);
-  const C rest0 = -rho * s0 / C(6), rest1 = -rho * s1 / C(6);
+  const C e9 = cdiv<9>(rt);
+  const C rest0 = cdiv<6>(-rho * s0), rest1 = cdiv<6>(-rho * s1);
   m[16] = op * (m[16] - e9 - rest0 - r3 * (xx0 + yy0)) + e9 + rest1 + r3 * (xx1 + yy1);
   m[17] = op * (m[17] - e9 - rest0 - r3 * (xx0 + zz0)) + e9 + rest1 + r3 * (xx1 + zz1);
   m[18] = op * (m[18] - e9 - rest0 - r3 * (yy0 + zz0)) + e9 + rest1 + r3 * (yy1 + zz1);
@@ -204,22 +219,23 @@ __device__ __forceinline__ void collide7(C* g, C Fbar, const Phys<C>& ph) {
   n4 = n4 - ph.vother * (n4 - ph.wbar * n0);
   n5 *= om;
   n6 *= om;
-  const C s6 = n4 / C(6);
-  const C a = (n5 + n6) / C(6);
+  const C s6 = cdiv<6>(n4);
+  const C a = cdiv<6>(n5 + n6);
   g[0] = n0 - n4 - ph.w0 * Fbar;
   g[1] = C(0.5) * n1 + s6 + a - ph.w1 * Fbar;
   g[2] = -C(0.5) * n1 + s6 + a - ph.w1 * Fbar;
-  g[3] = C(0.5) * n2 + s6 - n5 / C(3) + n6 / C(6) - ph.w1 * Fbar;
-  g[4] = -C(0.5) * n2 + s6 - n5 / C(3) + n6 / C(6) - ph.w1 * Fbar;
-  g[5] = C(0.5) * n3 + s6 + n5 / C(6) - n6 / C(3) - ph.w1 * Fbar;
-  g[6] = -C(0.5) * n3 + s6 + n5 / C(6) - n6 / C(3) - ph.w1 * Fbar;
+  const C n5_3 = cdiv<3>(n5), n5_6 = cdiv<6>(n5), n6_3 = cdiv<3>(n6), n6_6 = cdiv<6>(n6);
+  g[3] = C(0.5) * n2 + s6 - n5_3 + n6_6 - ph.w1 * Fbar;
+  g[4] = -C(0.5) * n2 + s6 - n5_3 + n6_6 - ph.w1 * Fbar;
+  g[5] = C(0.5) * n3 + s6 + n5_6 - n6_3 - ph.w1 * Fbar;
+  g[6] = -C(0.5) * n3 + s6 + n5_6 - n6_3 - ph.w1 * Fbar;
 }
 
 // eqs. (27)-(29): c_s^2 dT/dx_a = -varsigma_a m_a (dt = 1) with the
 // pre-collision first moments of g (their equilibrium part is zero).
 template <typename C>
 __device__ __forceinline__ void local_gradT(const C* g, const Phys<C>& ph, C& gx, C& gy, C& gz) {
-  const C k = -ph.vflux / ph.cs2T;
+  const C k = div(-ph.vflux, ph.cs2T);
   gx = k * (g[1] - g[2]);
   gy = k * (g[3] - g[4]);
   gz = k * (g[5] - g[6]);
