@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--variant-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
+                    help="only run a plain device copy of this size 3 times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -125,6 +127,15 @@ def main():
     from workloads import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": n * 4, "copies": 3}), flush=True)
+        return
     P.load_library()
     print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
     w = synth.named(args.workload)

@@ -27,6 +27,7 @@
 #pragma once
 
 #include <cstdlib>
+#include <type_traits>
 
 #include "lbm3d.h"
 #include "kernels_ref.h"
@@ -34,6 +35,11 @@
 namespace lbm {
 
 constexpr int FTX = 64;
+// cache policy of the population stores (2: non-temporal streaming stores)
+#ifndef LBM_STREAM_STORES
+#define LBM_STREAM_STORES 0
+#endif
+constexpr int kStoreCachePolicy = LBM_STREAM_STORES ? 2 : 0;
 
 template <typename C>
 struct FusedArgs {
@@ -42,6 +48,7 @@ struct FusedArgs {
   long long N;
   int zwall;  // 1: no-slip walls at z = 0 and z = nz - 1; 0: periodic z
   int tiles_x, ntiles, chunk;
+  int xcd_blocks;  // 1: each XCD owns a 2 x 4 block of the tile grid
   C wall_T[2];            // Dirichlet temperatures of the z = 0 and z = nz - 1 walls
   const double* wall_Tw[2];  // optional per-cell wall temperature fields (nx*ny)
   int* flag;
@@ -119,7 +126,7 @@ __device__ __forceinline__ typename Storage<S>::C ld_at(const S* plane, unsigned
 template <typename S>
 __device__ __forceinline__ void st_at(S* plane, unsigned bytes, unsigned voff, unsigned soff,
                                       typename Storage<S>::C v) {
-  Buf<S>::store(buffer_range(plane, bytes), voff, soff, v);
+  Buf<S>::template store<kStoreCachePolicy>(buffer_range(plane, bytes), voff, soff, v);
 }
 
 template <typename S, int TY>
@@ -144,7 +151,15 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   // consecutive tiles on one XCD (blocks are dealt to the 8 XCDs round-robin)
   if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
   const int tile = b % a.ntiles, chunk = b / a.ntiles;
-  const int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
+  int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
+  if (a.xcd_blocks) {
+    // XCD k (block index mod 8) owns tile block (k % 2, k / 2) of a 2 x 4
+    // split; its blocks are dealt row by row within that block
+    const int bxw = a.tiles_x / 2, byh = (a.ntiles / a.tiles_x) / 4;
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    x0 = ((xcd & 1) * bxw + local % bxw) * TX;
+    y0 = ((xcd >> 1) * byh + local / bxw) * TY;
+  }
   const int z0 = chunk * a.chunk, z1 = min(a.nz, z0 + a.chunk);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long long N = a.N;
@@ -225,49 +240,77 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
 #pragma unroll
     for (int i = 0; i < 7; ++i) l[19 + i] = ld_at(gz, G7, off, i * PB);
   };
+  // lanes without a halo cell load from beyond the descriptor range: the
+  // hardware returns 0 without a memory access, and the load count stays
+  // the same on every path (the compiler then waits only for these loads)
+  const unsigned hcolb_pf = has_halo ? hcolb : 0xFFFFFF00u;
   auto prefetch = [&](int zn) {
     load_cell(zn, colb, pfi);
-    if (has_halo) load_cell(zn, hcolb, pfh);
+    load_cell(zn, hcolb_pf, pfh);
   };
 #pragma unroll
   for (int i = 0; i < 26; ++i) pfi[i] = pfh[i] = C(0);
 
   const int p_begin = z0 - 2, p_end = z1 + 1;
+  // values of the plane being taken in: tile cell (fb, gc) and halo cell (hv, gv)
+  C hv[19], gv[7];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) hv[i] = C(0);
+#pragma unroll
+  for (int i = 0; i < 7; ++i) gv[i] = C(0);
+  auto take_prefetched = [&]() {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) fb[i] = pfi[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) gc[i] = pfi[19 + i];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) hv[i] = pfh[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) gv[i] = pfh[19 + i];
+  };
   if constexpr (PF) {
     int zf;
-    if (plane_of(p_begin, zf)) prefetch(zf);
+    if (plane_of(p_begin, zf)) {
+      prefetch(zf);
+      take_prefetched();
+    }
   }
-  for (int p = p_begin; p <= p_end; ++p) {
+  // One plane step of the march.  In the steady part of the march (ST) the
+  // planes p, p-1 and p-2 are interior planes of this chunk: no wrap, no wall
+  // and every stage runs, so each step issues the same memory operations.
+  auto step = [&](int p, auto steady) __attribute__((always_inline)) {
+    constexpr bool ST = decltype(steady)::value;
     const int k = p - p_begin;
     const int s3 = k % 3, s4 = k & 3, s2 = k & 1;
     int zp;
-    const bool exists = plane_of(p, zp);
+    const bool exists = ST ? (zp = p, true) : plane_of(p, zp);
     // ---------------------------------------------------------------- plane p: take the prefetched values
-    C hv[19], gv[7];
-    if (exists) {
-      C li[26];
-      if constexpr (!PF) load_cell(zp, colb, li);
-      const C* vi = PF ? pfi : li;
+    if constexpr (!PF) {
+      if (exists) {
+        C li[26];
+        load_cell(zp, colb, li);
 #pragma unroll
-      for (int i = 0; i < 19; ++i) fb[i] = vi[i];
+        for (int i = 0; i < 19; ++i) fb[i] = li[i];
 #pragma unroll
-      for (int i = 0; i < 7; ++i) gc[i] = vi[19 + i];
-      if constexpr (PF) {
-        if (has_halo) {
-#pragma unroll
-          for (int i = 0; i < 19; ++i) hv[i] = pfh[i];
-#pragma unroll
-          for (int i = 0; i < 7; ++i) gv[i] = pfh[19 + i];
-        }
+        for (int i = 0; i < 7; ++i) gc[i] = li[19 + i];
       }
     }
-    // issue the loads of plane p+1; they complete while plane p-1 and p-2 are updated
+    // with prefetch, fb/gc/hv/gv already hold plane p (taken in at the end of
+    // the previous step); issue the loads of plane p+1, which complete while
+    // planes p-1 and p-2 are updated
+    bool next_loaded = false;
     if constexpr (PF) {
       int zn;
-      if (p < p_end && plane_of(p + 1, zn)) prefetch(zn);
+      if (ST) {
+        prefetch(p + 1);
+        next_loaded = true;
+      } else if (p < p_end && plane_of(p + 1, zn)) {
+        prefetch(zn);
+        next_loaded = true;
+      }
     }
     if (exists) {
-      const bool wall_plane = a.zwall && (zp == 0 || zp == nz - 1);
+      const bool wall_plane = !ST && a.zwall && (zp == 0 || zp == nz - 1);
       const int zin = zp == 0 ? 1 : nz - 2;
       const int wk = zp == 0 ? 0 : 1;
       // eqs. (35)-(36) on a wall plane: g_b = w T_b + g(x_f) - w T(x_f), on deviations
@@ -341,14 +384,14 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     finish_pulls();
     const int q = p - 1;
     int zq;
-    const bool do_u = q >= z0 - 1 && plane_of(q, zq);
+    const bool do_u = ST ? (zq = q, true) : (q >= z0 - 1 && plane_of(q, zq));
     if (do_u) {
       // psi slots of planes q-1, q, q+1 (walls: the ghost layer mirrors the
       // first interior layer, eq. (37) with theta = 90 degrees)
       int sm = (k + 1) % 3, s0 = (k + 2) % 3, sp = s3;
-      if (a.zwall && zq == 0) sm = sp;
-      if (a.zwall && zq == nz - 1) sp = sm;
-      const bool wall_plane = a.zwall && (zq == 0 || zq == nz - 1);
+      if (!ST && a.zwall && zq == 0) sm = sp;
+      if (!ST && a.zwall && zq == nz - 1) sp = sm;
+      const bool wall_plane = !ST && a.zwall && (zq == 0 || zq == nz - 1);
       const int sq = (k + 1) & 1;  // ueq slot of plane q
       const int rq = (k + 3) & 3;  // rho slot of plane q
       auto force_at = [&](int e, C& Fx, C& Fy, C& Fz) {
@@ -385,15 +428,15 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         s_u[0][e_own] = ub[0];
         s_u[1][e_own] = ub[1];
         s_u[2][e_own] = ub[2];
-        if (q >= z0 && q < z1) {
+        if (ST || (q >= z0 && q < z1)) {
           collide19(fa, rho, rho - ph.rho_ref, uex, uey, uez, dux, duy, duz, ph);
           // destination planes q-1, q, q+1 (periodic wrap); at a wall the
           // links leaving the domain bounce back onto the opposite slot
-          const bool lo_out = zq == 0, hi_out = zq == nz - 1;
+          const bool lo_out = !ST && zq == 0, hi_out = !ST && zq == nz - 1;
           S* pm = fB + PS * 19 * (lo_out ? nz - 1 : zq - 1);
           S* p0 = fB + PS * 19 * zq;
           S* pp = fB + PS * 19 * (hi_out ? 0 : zq + 1);
-          if (!(a.zwall && (lo_out || hi_out))) {
+          if (ST || !(a.zwall && (lo_out || hi_out))) {
 #pragma unroll
             for (int i = 0; i < 19; ++i)
               st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
@@ -435,9 +478,9 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     // ---------------------------------------------------------------- plane p-2: D3Q7
     const int r = p - 2;
     int zr;
-    const bool r_exists = plane_of(r, zr);
+    const bool r_exists = ST ? (zr = r, true) : plane_of(r, zr);
     const C og1 = ga[1], og2 = ga[2], og3 = ga[3], og4 = ga[4], og6 = ga[6];
-    const bool do_g = r_exists && r >= z0 && r < z1;
+    const bool do_g = ST || (r_exists && r >= z0 && r < z1);
     if (do_g) {
       const C T = ph.T_ref + (ga[0] + ga[1] + ga[2] + ga[3] + ga[4] + ga[5] + ga[6]);
       C gx, gy, gz;
@@ -451,7 +494,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       {
         int zd = zr + 1;
         bool ok = true;
-        if (zd >= nz) {
+        if (!ST && zd >= nz) {
           if (a.zwall) ok = false; else zd = 0;
         }
         if (ok)
@@ -461,7 +504,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       {
         int zd = zr - 1;
         bool ok = true;
-        if (zd < 0) {
+        if (!ST && zd < 0) {
           if (a.zwall) ok = false; else zd = nz - 1;
         }
         if (ok)
@@ -506,6 +549,24 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     ua[0] = ub[0];
     ua[1] = ub[1];
     ua[2] = ub[2];
+    if constexpr (PF) {
+      if (next_loaded) take_prefetched();
+    }
+  };
+  if constexpr (PF) {
+    // warm-up, steady march, drain
+    const int s_lo = z0 + 3, s_hi = z1 - 2;
+    int p = p_begin;
+    for (; p <= p_end && p < s_lo; ++p) step(p, std::false_type{});
+    if (p <= s_hi) {
+      // nothing in flight on entry: inside the steady loop the wait for the
+      // prefetched plane then leaves the previous plane's stores outstanding
+      __builtin_amdgcn_s_waitcnt(0);
+      for (; p <= s_hi; ++p) step(p, std::true_type{});
+    }
+    for (; p <= p_end; ++p) step(p, std::false_type{});
+  } else {
+    for (int p = p_begin; p <= p_end; ++p) step(p, std::false_type{});
   }
   __syncthreads();
   finish_pulls();
@@ -553,6 +614,10 @@ struct FusedImpl {
     a.ntiles = a.tiles_x * (p.ny / TY);
     a.chunk = chunk_planes > 0 ? chunk_planes : p.nz;
     const int nchunks = (p.nz + a.chunk - 1) / a.chunk;
+    a.xcd_blocks = 0;
+    if (const char* ev = std::getenv("LBM_FUSED_MAP"))
+      a.xcd_blocks = std::atoi(ev) == 1 && nchunks == 1 && a.tiles_x % 2 == 0 && (p.ny / TY) % 4 == 0 &&
+                     a.ntiles % 8 == 0;
     a.wall_T[0] = (C)p.face_T[4];
     a.wall_T[1] = (C)p.face_T[5];
     a.wall_Tw[0] = Tw0;

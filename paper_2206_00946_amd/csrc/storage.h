@@ -69,9 +69,10 @@ struct Buf<double> {
   static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   }
+  template <int CP = 0>
   static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, CP);
   }
 };
 
@@ -80,8 +81,9 @@ struct Buf<float> {
   static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
+  template <int CP = 0>
   static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, CP);
   }
 };
 
@@ -90,9 +92,10 @@ struct Buf<_Float16> {
   static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     return static_cast<float>(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
   }
+  template <int CP = 0>
   static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, static_cast<_Float16>(v)), r, voff,
-                                          soff, 0);
+                                          soff, CP);
   }
 };
 
@@ -103,10 +106,11 @@ struct Buf<bf16> {
     h.bits = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
     return Storage<bf16>::load(&h);
   }
+  template <int CP = 0>
   static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
     bf16 h;
     Storage<bf16>::store(&h, v);
-    __builtin_amdgcn_raw_buffer_store_b16(h.bits, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(h.bits, r, voff, soff, CP);
   }
 };
 
