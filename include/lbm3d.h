@@ -153,6 +153,39 @@ lbm_status lbm_populations(lbm_ctx* ctx, double* f, double* g);
  * evaporated mass), reduced on the GPU in a fixed order.  Synchronous. */
 lbm_status lbm_reduce(lbm_ctx* ctx, lbm_diag* out);
 
+/* Discrete adjoint of nsteps time steps from the current state t0.
+ * Objective (objective = 0): the evaporated mass J = M(t0) - M(t0 + N),
+ * M = sum over all cells of rho (rho_out on outlet nodes), the quantity
+ * behind the d^2 law (Sec. 4.2, eq. (56)).  The adjoint reverses every stage
+ * of the step (Sec. 2, 3.1, 3.3: collisions, streaming, blend, source,
+ * force and divergence stencils, wetting ghost layer eq. (37), outlet fill,
+ * Dirichlet extrapolation eqs. (35)-(36)) and returns
+ *   dJ_dTw[x + nx*y]: derivative with respect to the Dirichlet temperature
+ *                     of node (x, y) of face spec->wall_face (the T_w field
+ *                     when one is set, else the uniform face_T), nx*ny values;
+ *   *dJ_dkappa:       derivative with respect to kappa_w (eq. (37)); the
+ *                     derivative of |grad_t psi| at 0 is taken as 0.
+ * The forward trajectory is recomputed from ceil(N / L) stored states, L =
+ * ceil(N / K), K = n_checkpoints (0: ceil(sqrt(N))); the workspace (see
+ * lbm_adjoint_bytes) is allocated for the call and released before it
+ * returns (LBM_ENOMEM if it does not fit).  Requires periodic x and y faces
+ * (LBM_EUNSUPPORTED otherwise) and a non-periodic wall_face (LBM_EINVAL).
+ * On return the context holds the state at t0 + N, as after lbm_step(N).
+ * J, dJ_dTw and dJ_dkappa may be NULL; dJ_dTw is a device pointer when
+ * dst_on_device = 1.  Synchronous. */
+typedef struct {
+  int32_t nsteps;         /* N >= 1 */
+  int32_t n_checkpoints;  /* K >= 0 */
+  int32_t objective;      /* 0: evaporated mass */
+  int32_t wall_face;      /* 4 (-z) or 5 (+z) */
+} lbm_adjoint_spec;
+
+/* Device bytes lbm_adjoint allocates for spec on this context. */
+lbm_status lbm_adjoint_bytes(const lbm_ctx* ctx, const lbm_adjoint_spec* spec, size_t* bytes);
+
+lbm_status lbm_adjoint(lbm_ctx* ctx, const lbm_adjoint_spec* spec, double* J, double* dJ_dTw, double* dJ_dkappa,
+                       int32_t dst_on_device);
+
 /* Message of the last failing call on ctx (or of the last failing
  * lbm_create when ctx is NULL).  Valid until the next call on ctx. */
 const char* lbm_last_error(const lbm_ctx* ctx);

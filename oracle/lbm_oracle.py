@@ -42,6 +42,11 @@ the design notes of the repository):
   * edge nodes of several Dirichlet faces take T_b and rho_out from the first
     face in the priority order (-z, +z, -y, +y, -x, +x).
 
+Every step function is written for real or complex arrays alike (the
+complex-step derivative of ``oracle/gradients.py`` runs the same code on
+complex inputs); comparisons only ever see the real parts of masks that
+do not depend on the state.
+
 Parity status: every function is pinned by tests under ``tests/`` (algebraic
 identities, invariants, closed forms, brute force, printed special cases),
 except the physics-only quantities listed in the design notes (coexistence
@@ -447,7 +452,7 @@ def interaction_force(psi, p: Params):
     """eq. (6): F = -G psi(x) sum_{i=1..18} varpi(|c_i|^2) psi(x + c_i) c_i,
     varpi(1) = 1/6, varpi(2) = 1/12.  F_ext = 0 (gravity neglected, Sec. 4.3)."""
     P = pad_psi(psi, p)
-    acc = np.zeros((3,) + psi.shape)
+    acc = np.zeros((3,) + psi.shape, dtype=np.result_type(P, np.float64))
     for i in range(1, 19):
         c = C19[i]
         varpi = 1.0 / 6.0 if int(np.dot(c, c)) == 1 else 1.0 / 12.0
@@ -462,7 +467,7 @@ def divergence(u, p: Params):
     """Isotropic central divergence on the D3Q19 stencil (Sec. 2.2, end):
     div u = (1/c_s^2) sum_i w_i c_i . u(x + c_i)."""
     pads = [pad_velocity_component(u[a], p) for a in range(3)]
-    div = np.zeros(u.shape[1:])
+    div = np.zeros(u.shape[1:], dtype=np.result_type(u, np.float64))
     for i in range(1, 19):
         c = C19[i]
         for a in range(3):
@@ -511,9 +516,11 @@ def thermal_dirichlet(g, p: Params, Tw: Optional[Dict[int, np.ndarray]] = None):
     k = prio[bz, by, bx]
     Tb = np.array(p.face_T, dtype=np.float64)[k]
     if Tw:
+        Tb = Tb.astype(np.result_type(Tb, *[np.asarray(v) for v in Tw.values()]))
         for face, field2d in Tw.items():
             sel = k == face
             Tb[sel] = field2d[by[sel], bx[sel]]
+    g = g.astype(np.result_type(g, Tb), copy=False)
     g[:, bz, by, bx] = w[:, None] * Tb[None, :] + gf - w[:, None] * Tf[None, :]
     return g
 
@@ -561,7 +568,7 @@ def zou_he_face(f, F, rho_out, k):
     for t in tangents:
         delta_t[t] = -0.5 * (f[cn == 0] * C19[cn == 0, t][:, None]).sum(axis=0) - 0.25 * F[t]
     delta_n = -Fn / 8.0
-    out = f.copy()
+    out = f.astype(np.result_type(f, F))
     for i in np.nonzero(cn == -1)[0]:
         j = OPP19[i]
         if np.all(C19[i] == -n):
@@ -582,7 +589,7 @@ def zou_he(f, F, p: Params):
     face_only, edge, any_p, rho_out, inward = pressure_nodes(p)
     if not any_p.any():
         return f
-    f = f.copy()
+    f = f.astype(np.result_type(f, F))
     for k in range(6):
         m = face_only[k]
         if m is None or not m.any():

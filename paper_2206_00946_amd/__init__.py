@@ -2,4 +2,4 @@
 Boltzmann step (Huang, Wang, He & Huang, arXiv 2206.00946): a HIP library
 for gfx950 behind the C ABI of include/lbm3d.h, with a ctypes binding."""
 from .lbm3d import (Lbm3D, LbmError, LbmParams, from_workload, load_library, make_params,  # noqa: F401
-                    params_from_workload, FP64, FP32_DEV, FP16_DEV, BF16_DEV, PERIODIC, WALL, PRESSURE)
+                    params_from_workload, evaporated_mass_function, FP64, FP32_DEV, FP16_DEV, BF16_DEV, PERIODIC, WALL, PRESSURE)

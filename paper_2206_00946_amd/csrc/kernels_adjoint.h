@@ -1,0 +1,428 @@
+// Discrete adjoint of one coupled time step (reverse mode of the stages of
+// Huang, Wang, He & Huang, arXiv 2206.00946, Sec. 2 and 3), for domains
+// periodic in x and y with periodic, wall or pressure z faces.
+//
+// Forward stages of step t (state s_t -> s_{t+1}) and their reverse, in the
+// order the kernels below run them:
+//   S9/S10 push + blend, S8 D3Q7 collision, S7 D3Q19 collision, S6 source
+//                                            -> k_adj_collide (per cell, gathers)
+//   S6 divergence stencil, S5 velocities, S4 outlet fill
+//                                            -> k_adj_velocity
+//   eq. (37) wetting ghost layer             -> k_adj_ghost (wall planes)
+//   S3 force stencil, S2 psi, S1 moments     -> k_adj_psi
+//   S0 thermal Dirichlet (eqs. (35)-(36))    -> k_adj_dirichlet (face planes)
+// Each kernel consumes the forward fields of step t (rho, T, psi, u_eq, du
+// recomputed from the stored state) and the adjoint of s_{t+1}; together they
+// give the adjoint of s_t and add the step's contribution to dJ/dT_w and
+// dJ/dkappa_w.  Adjoints are held in the compute type C in the population
+// layout of the state; gradients accumulate in FP64.
+#pragma once
+
+#include "adjoint.h"
+#include "kernels_ref.h"
+
+namespace lbm {
+
+// z one step outside the domain: wrap if periodic and report whether the
+// node exists.
+__device__ __forceinline__ bool z_inside(const Geom& g, int& z) {
+  if (z >= 0 && z < g.nz) return true;
+  if (g.face[z < 0 ? 4 : 5] == FACE_PERIODIC) {
+    z = wrapp(z, g.nz);
+    return true;
+  }
+  return false;
+}
+
+template <typename C>
+__device__ __forceinline__ C varpi(int i) {
+  return i < 7 ? C(1) / C(6) : C(1) / C(12);
+}
+
+// adjoint state at t = N of J = M(0) - M(N): dJ/df_i = -1 where rho = sum f
+template <typename C>
+__global__ void __launch_bounds__(256) k_adj_seed(C* __restrict__ lf, C* __restrict__ lg, Geom g) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  const Node n = classify(g, x, y, z);
+  const C v = n.pressure ? C(0) : C(-1);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) lf[pidx(g, 19, i, x, y, z)] = v;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) lg[pidx(g, 7, i, x, y, z)] = C(0);
+}
+
+// Reverse of S10, S9, S8, S7 and the local part of S6 at every cell x.
+//   lfi, lgi: adjoint of s_{t+1}; gA: post-Dirichlet g of s_t; gnext: g of s_{t+1}
+//   lfo, lgo: partial adjoint of the completed f, g of s_t
+//   a_rho, a_T: partial adjoints of rho and T; a_ueq, a_du: of u_eq and du
+//   (the wall override of S5 already applied); a_div: of div u at x
+template <typename S>
+__global__ void __launch_bounds__(256)
+    k_adj_collide(const typename Storage<S>::C* __restrict__ lfi, const typename Storage<S>::C* __restrict__ lgi,
+                  const S* __restrict__ gA, const S* __restrict__ gnext,
+                  const typename Storage<S>::C* __restrict__ rho_f, const typename Storage<S>::C* __restrict__ T_f,
+                  const typename Storage<S>::C* __restrict__ ueq, const typename Storage<S>::C* __restrict__ du,
+                  typename Storage<S>::C* __restrict__ lfo, typename Storage<S>::C* __restrict__ lgo,
+                  typename Storage<S>::C* __restrict__ a_rho, typename Storage<S>::C* __restrict__ a_T,
+                  typename Storage<S>::C* __restrict__ a_ueq, typename Storage<S>::C* __restrict__ a_du,
+                  typename Storage<S>::C* __restrict__ a_div, Geom g, Phys<typename Storage<S>::C> ph) {
+  using C = typename Storage<S>::C;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  const long long N = g.N;
+  const Node n = classify(g, x, y, z);
+  const C rho = rho_f[c], T = T_f[c];
+  const C ux = ueq[c], uy = ueq[c + N], uz = ueq[c + 2 * N];
+  const C dux = du[c], duy = du[c + N], duz = du[c + 2 * N];
+
+  // S9: f*_i(x) went to slot i at x + c_i, to slot opp(i) at x (wall), or
+  // left the domain (outlet)
+  C fsb[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int xd = wrapp(x + CX[i], g.nx), yd = wrapp(y + CY[i], g.ny);
+    int zd = z + CZ[i];
+    if (z_inside(g, zd)) fsb[i] = lfi[pidx(g, 19, i, xd, yd, zd)];
+    else if (g.face[zd < 0 ? 4 : 5] == FACE_WALL) fsb[i] = lfi[pidx(g, 19, opp19(i), x, y, z)];
+    else fsb[i] = C(0);
+  }
+  // S10: g*_i(x) enters the blend at y = x + c_i with weight 1/(rho(y) c_v)
+  C gsb[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const int xd = wrapp(x + CX[i], g.nx), yd = wrapp(y + CY[i], g.ny);
+    int zd = z + CZ[i];
+    gsb[i] = C(0);
+    if (z_inside(g, zd)) {
+      const long long cd = cell_index(g, xd, yd, zd);
+      gsb[i] = lgi[pidx(g, 7, i, xd, yd, zd)] / (rho_f[cd] * ph.cv);
+    }
+  }
+  C fb[19], gb[7];
+  C rb = C(0);
+  C ub[3] = {C(0), C(0), C(0)}, dub[3] = {C(0), C(0), C(0)};
+  collide19_adj(fsb, rho, ux, uy, uz, dux, duy, duz, ph, fb, rb, ub, dub);  // S7
+  C Fbarb;
+  collide7_adj(gsb, ph, gb, Fbarb);  // S8
+
+  // S6 (local part): Fbar = rho c_v u . grad T + T (dp/dT) div u
+  C gp[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) gp[i] = Storage<S>::load(gA + pidx(g, 7, i, x, y, z));
+  C gx, gy, gz;
+  local_gradT(gp, ph, gx, gy, gz);
+  const C rux = ux + C(0.5) * dux, ruy = uy + C(0.5) * duy, ruz = uz + C(0.5) * duz;
+  C div = C(0);
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    C vx, vy, vz;
+    u_at(ueq, du, g, x + CX[i], y + CY[i], z + CZ[i], vx, vy, vz);
+    div += C(3) * w19<C>(i) * (C(CX[i]) * vx + C(CY[i]) * vy + C(CZ[i]) * vz);
+  }
+  C dp_dr, dpdT, dpdT_dr, dpdT_dT;
+  pr_partials(rho, T, ph, dp_dr, dpdT, dpdT_dr, dpdT_dT);
+  rb += Fbarb * (ph.cv * (rux * gx + ruy * gy + ruz * gz) + T * dpdT_dr * div);
+  C Tb = Fbarb * (dpdT + T * dpdT_dT) * div;
+  const C divb = Fbarb * T * dpdT;
+  const C rcv = Fbarb * rho * ph.cv;
+  const C urb[3] = {rcv * gx, rcv * gy, rcv * gz};
+  const C kq = -ph.vflux / ph.cs2T;  // grad T = kq * (first moments of g)
+  gb[1] += kq * rcv * rux;
+  gb[2] -= kq * rcv * rux;
+  gb[3] += kq * rcv * ruy;
+  gb[4] -= kq * rcv * ruy;
+  gb[5] += kq * rcv * ruz;
+  gb[6] -= kq * rcv * ruz;
+
+  // S10 with x as the destination: g_i(x, t+1) = g_i + (g*_i(src) - g_i) / (rho c_v)
+  const C inv = C(1) / (rho * ph.cv);
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const C l = lgi[pidx(g, 7, i, x, y, z)];
+    int zs = z - CZ[i];
+    if (z_inside(g, zs)) {
+      gb[i] += l * (C(1) - inv);
+      if (n.count == 0) {
+        // the adjoint of s_{t+1} vanishes on bounded-face nodes, where the
+        // next step's Dirichlet condition overwrites g
+        const C gn = Storage<S>::load(gnext + pidx(g, 7, i, x, y, z));
+        rb -= l * (gn - gp[i]) / rho;
+      }
+    } else {
+      gb[i] += l;
+    }
+  }
+  // S5: u = u_eq + du/2, except at wall nodes where u = 0 and u_eq = -du/2
+  if (n.wall) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dub[a] -= C(0.5) * ub[a];
+      ub[a] = C(0);
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ub[a] += urb[a];
+      dub[a] += C(0.5) * urb[a];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 19; ++i) lfo[pidx(g, 19, i, x, y, z)] = fb[i];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) lgo[pidx(g, 7, i, x, y, z)] = gb[i];
+  a_rho[c] = rb;
+  a_T[c] = Tb;
+  a_div[c] = divb;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    a_ueq[c + a * N] = ub[a];
+    a_du[c + a * N] = dub[a];
+  }
+}
+
+// Reverse of the divergence stencil (every reader of u at y), of S5 and of
+// the outlet fill.  On return a_ueq holds the adjoint of the momentum j,
+// a_du the adjoint of the force F, a_rho the partial adjoint of rho; at
+// outlet nodes the adjoint of f is final (lfo) and a_ueq, a_rho are zero.
+template <typename C>
+__global__ void __launch_bounds__(256)
+    k_adj_velocity(C* __restrict__ lfo, const C* __restrict__ a_div, C* __restrict__ a_ueq, C* __restrict__ a_du,
+                   C* __restrict__ a_rho, const C* __restrict__ rho_f, const C* __restrict__ ueq,
+                   const C* __restrict__ du, Geom g) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  const long long N = g.N;
+  const Node n = classify(g, x, y, z);
+  C ueb[3], dub[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ueb[a] = a_ueq[c + a * N];
+    dub[a] = a_du[c + a * N];
+  }
+  if (!n.wall) {
+    // readers of u(y): x = y - c_i directly, and on an outlet plane the
+    // same-plane readers whose ghost neighbour is a copy of y
+    C vb[3] = {C(0), C(0), C(0)};
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      const int xr = wrapp(x - CX[i], g.nx), yr = wrapp(y - CY[i], g.ny);
+      int zr = z - CZ[i];
+      C d = C(0);
+      if (z_inside(g, zr)) d += a_div[cell_index(g, xr, yr, zr)];
+      const int zo = z + CZ[i];
+      if ((zo < 0 || zo >= g.nz) && g.face[zo < 0 ? 4 : 5] == FACE_PRESSURE) d += a_div[cell_index(g, xr, yr, z)];
+      d *= C(3) * w19<C>(i);
+      vb[0] += C(CX[i]) * d;
+      vb[1] += C(CY[i]) * d;
+      vb[2] += C(CZ[i]) * d;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ueb[a] += vb[a];
+      dub[a] += C(0.5) * vb[a];
+    }
+  }
+  const C rho = rho_f[c];
+  C rb = a_rho[c];
+  C jb[3], Fb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // u_eq = j / rho (the wall value was moved to du in k_adj_collide), du = F / rho
+    jb[a] = ueb[a] / rho;
+    Fb[a] = dub[a] / rho;
+    rb -= (ueb[a] * ueq[c + a * N] + dub[a] * du[c + a * N]) / rho;
+  }
+  if (n.pressure) {
+    C fb[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+      fb[i] = lfo[pidx(g, 19, i, x, y, z)] + C(CX[i]) * jb[0] + C(CY[i]) * jb[1] + C(CZ[i]) * jb[2];
+    outlet_fill_adj(fb, n.pface, Fb);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) lfo[pidx(g, 19, i, x, y, z)] = fb[i];
+    jb[0] = jb[1] = jb[2] = C(0);
+    rb = C(0);  // rho = rho_out is fixed on outlet nodes
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    a_ueq[c + a * N] = jb[a];
+    a_du[c + a * N] = Fb[a];
+  }
+  a_rho[c] = rb;
+}
+
+// Reverse of the wetting ghost layer of eq. (37) on each wall face, one
+// thread per (x, y): psi_ghost = psi(x, y, z_in) + kappa_w |grad_t psi(x, y, z_w)|.
+// gadj = adjoint of psi_ghost (from the force of the wall-plane readers);
+// ax, ay route it to the tangential differences; kap = its kappa_w part.
+// Planes are indexed face * nx*ny + x + nx*y, face 0 = -z, 1 = +z.
+template <typename C>
+__global__ void __launch_bounds__(256) k_adj_ghost(const C* __restrict__ Fb, const C* __restrict__ psi,
+                                                   C* __restrict__ gadj, C* __restrict__ ax, C* __restrict__ ay,
+                                                   C* __restrict__ kap, Geom g, Phys<C> ph) {
+  const long long P = (long long)g.nx * g.ny;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P) return;
+  const int x = (int)(t % g.nx), y = (int)(t / g.nx);
+  const long long N = g.N;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (g.face[4 + s] != FACE_WALL) {
+      kap[s * P + t] = C(0);
+      continue;
+    }
+    const int zw = s ? g.nz - 1 : 0;
+    const int out = s ? 1 : -1;
+    C G = C(0);
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      if (CZ[i] != out) continue;
+      const long long cr = cell_index(g, wrapp(x - CX[i], g.nx), wrapp(y - CY[i], g.ny), zw);
+      G += -ph.G * psi[cr] * varpi<C>(i) *
+           (C(CX[i]) * Fb[cr] + C(CY[i]) * Fb[cr + N] + C(CZ[i]) * Fb[cr + 2 * N]);
+    }
+    const C dx = psi[cell_index(g, wrapp(x + 1, g.nx), y, zw)] - psi[cell_index(g, wrapp(x - 1, g.nx), y, zw)];
+    const C dy = psi[cell_index(g, x, wrapp(y + 1, g.ny), zw)] - psi[cell_index(g, x, wrapp(y - 1, g.ny), zw)];
+    const C sq = sqrt(dx * dx + dy * dy);
+    gadj[s * P + t] = G;
+    kap[s * P + t] = G * sq;
+    // d sqrt(s) at s = 0 is taken as 0
+    ax[s * P + t] = sq > C(0) ? G * ph.kappa_w * dx / sq : C(0);
+    ay[s * P + t] = sq > C(0) ? G * ph.kappa_w * dy / sq : C(0);
+  }
+}
+
+// Reverse of S3 (force stencil, with every ghost rule), S2 (psi) and S1
+// (rho = sum f, T = sum g).  Completes the adjoint of the completed f and g
+// of s_t (lfo, lgo).
+template <typename C>
+__global__ void __launch_bounds__(256)
+    k_adj_psi(C* __restrict__ lfo, C* __restrict__ lgo, const C* __restrict__ a_rho, const C* __restrict__ a_T,
+              const C* __restrict__ jb_f, const C* __restrict__ Fb, const C* __restrict__ psi,
+              const C* __restrict__ rho_f, const C* __restrict__ T_f, const C* __restrict__ gadj,
+              const C* __restrict__ ax, const C* __restrict__ ay, Geom g, Phys<C> ph) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  const long long N = g.N;
+  const long long P = (long long)g.nx * g.ny;
+  const Node n = classify(g, x, y, z);
+  // F(y) = -G psi(y) sum_i varpi_i c_i psi(y + c_i)
+  C acx = C(0), acy = C(0), acz = C(0);
+  C pb = C(0);
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    const C pn = psi_at(psi, g, ph.kappa_w, x + CX[i], y + CY[i], z + CZ[i]);
+    acx += varpi<C>(i) * C(CX[i]) * pn;
+    acy += varpi<C>(i) * C(CY[i]) * pn;
+    acz += varpi<C>(i) * C(CZ[i]) * pn;
+    // y as the neighbour x + c_i of the readers x = y - c_i, and of the
+    // same-plane readers beyond an outlet (ghost = copy of y)
+    const int xr = wrapp(x - CX[i], g.nx), yr = wrapp(y - CY[i], g.ny);
+    int zr = z - CZ[i];
+    const C wc = -ph.G * varpi<C>(i);
+    if (z_inside(g, zr)) {
+      const long long cr = cell_index(g, xr, yr, zr);
+      pb += wc * psi[cr] * (C(CX[i]) * Fb[cr] + C(CY[i]) * Fb[cr + N] + C(CZ[i]) * Fb[cr + 2 * N]);
+    }
+    const int zo = z + CZ[i];
+    if ((zo < 0 || zo >= g.nz) && g.face[zo < 0 ? 4 : 5] == FACE_PRESSURE) {
+      const long long cr = cell_index(g, xr, yr, z);
+      pb += wc * psi[cr] * (C(CX[i]) * Fb[cr] + C(CY[i]) * Fb[cr + N] + C(CZ[i]) * Fb[cr + 2 * N]);
+    }
+  }
+  pb += -ph.G * (acx * Fb[c] + acy * Fb[c + N] + acz * Fb[c + 2 * N]);
+  // wetting ghost layers: psi(x, y, z_in) enters directly, the wall plane
+  // through the tangential differences
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (g.face[4 + s] != FACE_WALL) continue;
+    const int zw = s ? g.nz - 1 : 0;
+    const int zi = s ? g.nz - 2 : 1;
+    const long long o = s * P;
+    if (z == zi) pb += gadj[o + x + (long long)g.nx * y];
+    if (z == zw) {
+      pb += ax[o + wrapp(x - 1, g.nx) + (long long)g.nx * y] - ax[o + wrapp(x + 1, g.nx) + (long long)g.nx * y] +
+            ay[o + x + (long long)g.nx * wrapp(y - 1, g.ny)] - ay[o + x + (long long)g.nx * wrapp(y + 1, g.ny)];
+    }
+  }
+  // eq. (7): psi = sqrt(2 (p - rho/3) / G)
+  const C rho = rho_f[c], T = T_f[c], ps = psi[c];
+  C dp_dr, dpdT, dpdT_dr, dpdT_dT;
+  pr_partials(rho, T, ph, dp_dr, dpdT, dpdT_dr, dpdT_dT);
+  const C q = ps > C(0) ? pb / (ph.G * ps) : C(0);
+  const C Tb = a_T[c] + q * dpdT;
+  if (!n.pressure) {
+    const C rb = a_rho[c] + q * (dp_dr - C(1) / C(3));
+    const C jx = jb_f[c], jy = jb_f[c + N], jz = jb_f[c + 2 * N];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const long long k = pidx(g, 19, i, x, y, z);
+      lfo[k] += rb + C(CX[i]) * jx + C(CY[i]) * jy + C(CZ[i]) * jz;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 7; ++i) lgo[pidx(g, 7, i, x, y, z)] += Tb;
+}
+
+// Reverse of S0 on the z faces, one thread per (x, y): g_i(x_b) = w_i T_b +
+// g_i(x_f) - w_i sum_j g_j(x_f).  Adds sum_i w_i gb_i(x_b) to dJ/dT_b of the
+// selected face and clears the adjoint of the overwritten g(x_b).
+template <typename C>
+__global__ void __launch_bounds__(256) k_adj_dirichlet(C* __restrict__ lgo, double* __restrict__ grad_Tw,
+                                                       int grad_face, Geom g, Phys<C> ph) {
+  const long long P = (long long)g.nx * g.ny;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P) return;
+  const int x = (int)(t % g.nx), y = (int)(t / g.nx);
+  for (int s = 0; s < 2; ++s) {
+    const int k = 4 + s;
+    if (g.face[k] == FACE_PERIODIC) continue;
+    const int zb = s ? g.nz - 1 : 0;
+    const int zf = s ? g.nz - 2 : 1;
+    C l[7];
+    C S = C(0);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      l[i] = lgo[pidx(g, 7, i, x, y, zb)];
+      S += (i == 0 ? ph.w0 : ph.w1) * l[i];
+    }
+    if (k == grad_face) grad_Tw[t] += (double)S;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      lgo[pidx(g, 7, i, x, y, zf)] += l[i] - S;
+      lgo[pidx(g, 7, i, x, y, zb)] = C(0);
+    }
+  }
+}
+
+// Fixed-order sum of n values into *acc (one workgroup).
+template <typename C>
+__global__ void __launch_bounds__(RED_THREADS) k_accumulate(const C* __restrict__ v, long long n,
+                                                            double* __restrict__ acc) {
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) s += (double)v[i];
+  __shared__ double red[RED_THREADS / 64];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+    acc[0] += t;
+  }
+}
+
+}  // namespace lbm

@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) k_macro(const S* __restrict__ fpop, const
 // k: the +z derivation mapped to face k by the lattice symmetry taking its
 // outward normal to +z.  f holds deviations; unknowns (c.n = -1) are filled.
 template <typename C>
-__device__ __forceinline__ void outlet_fill(C* f, int k, C rho_out, const C* F, const Phys<C>& ph) {
+__host__ __device__ __forceinline__ void outlet_fill(C* f, int k, C rho_out, const C* F, const Phys<C>& ph) {
   const int a = k >> 1;
   const int s = (k & 1) ? 1 : -1;
   C sig0 = C(0), sig1 = C(0), t0 = C(0), t1 = C(0);

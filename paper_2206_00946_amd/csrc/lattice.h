@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 namespace lbm {
 
 enum { FACE_PERIODIC = 0, FACE_WALL = 1, FACE_PRESSURE = 2 };
@@ -41,28 +43,35 @@ struct Phys {
 
 // ---------------------------------------------------------------- arithmetic
 // FP32 uses the hardware reciprocal and square root (about 1 ulp); FP64 keeps
-// correctly rounded division and square root.
+// correctly rounded division and square root.  The host versions exist for
+// the CPU unit checks of the per-cell arithmetic.
+#if defined(__HIP_DEVICE_COMPILE__)
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double div(double a, double b) { return a / b; }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+#else
+inline float rcp(float x) { return 1.0f / x; }
+inline float div(float a, float b) { return a / b; }
+inline float fsqrt(float x) { return std::sqrt(x); }
+#endif
+__host__ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__host__ __device__ __forceinline__ double div(double a, double b) { return a / b; }
+__host__ __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 // division by a small integer constant: a multiplication for FP32
 template <int K>
-__device__ __forceinline__ float cdiv(float x) { return x * (1.0f / K); }
+__host__ __device__ __forceinline__ float cdiv(float x) { return x * (1.0f / K); }
 template <int K>
-__device__ __forceinline__ double cdiv(double x) { return x / K; }
+__host__ __device__ __forceinline__ double cdiv(double x) { return x / K; }
 
 // ---------------------------------------------------------------- EOS
 template <typename C>
-__device__ __forceinline__ C pr_xi_sq_root(C T, const Phys<C>& ph) {
+__host__ __device__ __forceinline__ C pr_xi_sq_root(C T, const Phys<C>& ph) {
   // 1 + kappa (1 - sqrt(T/Tc)), whose square is xi(T)
   return C(1) + ph.kpr * (C(1) - fsqrt(div(T, ph.Tc)));
 }
 
 template <typename C>
-__device__ __forceinline__ C pr_pressure(C rho, C T, const Phys<C>& ph) {
+__host__ __device__ __forceinline__ C pr_pressure(C rho, C T, const Phys<C>& ph) {
   const C s = pr_xi_sq_root(T, ph);
   const C br = ph.b * rho;
   return div(rho * ph.R * T, C(1) - br) - div(ph.a * (s * s) * rho * rho, C(1) + C(2) * br - br * br);
@@ -70,7 +79,7 @@ __device__ __forceinline__ C pr_pressure(C rho, C T, const Phys<C>& ph) {
 
 // (d p / d T) at constant rho
 template <typename C>
-__device__ __forceinline__ C pr_dpdT(C rho, C T, const Phys<C>& ph) {
+__host__ __device__ __forceinline__ C pr_dpdT(C rho, C T, const Phys<C>& ph) {
   const C s = pr_xi_sq_root(T, ph);
   const C dxi = div(-ph.kpr * s, fsqrt(T * ph.Tc));
   const C br = ph.b * rho;
@@ -79,12 +88,12 @@ __device__ __forceinline__ C pr_dpdT(C rho, C T, const Phys<C>& ph) {
 
 // radicand of eq. (7): 2 (p - rho c_s^2) / G with c_s^2 = 1/3
 template <typename C>
-__device__ __forceinline__ C psi_radicand(C rho, C T, const Phys<C>& ph) {
+__host__ __device__ __forceinline__ C psi_radicand(C rho, C T, const Phys<C>& ph) {
   return div(C(2) * (pr_pressure(rho, T, ph) - cdiv<3>(rho)), ph.G);
 }
 
 template <typename C>
-__device__ __forceinline__ bool nonphysical(C rho, C T, C rad, const Phys<C>& ph) {
+__host__ __device__ __forceinline__ bool nonphysical(C rho, C T, C rad, const Phys<C>& ph) {
   // written so that NaN in any input also trips the flag
   return !(rho > C(0)) || !(rho * ph.b < C(1)) || !(T > C(0)) || !(rad >= C(0));
 }
@@ -94,7 +103,7 @@ __device__ __forceinline__ bool nonphysical(C rho, C T, C rad, const Phys<C>& ph
 // (monomials 1, x, y, z, |c|^2, 2x^2-y^2-z^2, y^2-z^2, xy, xz, yz, x^2y, xy^2,
 // x^2z, xz^2, y^2z, yz^2, x^2y^2, x^2z^2, y^2z^2).
 template <typename C>
-__device__ __forceinline__ void moments19(const C* f, C* m) {
+__host__ __device__ __forceinline__ void moments19(const C* f, C* m) {
   const C ax = f[1] + f[2], ay = f[3] + f[4], az = f[5] + f[6];
   const C dxy = f[7] + f[8] + f[9] + f[10];
   const C dxz = f[11] + f[12] + f[13] + f[14];
@@ -127,7 +136,7 @@ __device__ __forceinline__ void moments19(const C* f, C* m) {
 // quadruple from its four moments, the axis pairs from the second-order
 // moments, the rest population from m0 and m4.
 template <typename C>
-__device__ __forceinline__ void populations19(const C* m, C* f) {
+__host__ __device__ __forceinline__ void populations19(const C* m, C* f) {
   const C q = C(0.25);
   f[7] = q * (m[16] + m[10] + m[11] + m[7]);
   f[8] = q * (m[16] - m[10] - m[11] + m[7]);
@@ -165,7 +174,7 @@ __device__ __forceinline__ void populations19(const C* m, C* f) {
 // eq. (10) (e: moments of the rest weights, 1 at rows 0 and 4, 1/9 at rows
 // 16-18).  f is overwritten by the post-collision deviations.
 template <typename C>
-__device__ __forceinline__ void collide19(C* f, C rho, C rt, C ux, C uy, C uz, C dux, C duy,
+__host__ __device__ __forceinline__ void collide19(C* f, C rho, C rt, C ux, C uy, C uz, C dux, C duy,
                                           C duz, const Phys<C>& ph) {
   C m[19];
   moments19(f, m);
@@ -205,7 +214,7 @@ __device__ __forceinline__ void collide19(C* f, C rho, C rt, C ux, C uy, C uz, C
 // deviations: n = M gt, n* = n - L (n - (Tt, 0, 0, 0, wbar Tt, 0, 0)),
 // gt* = M^-1 n* - w_i Fbar (source of eq. (15)).  Tt = T - T_ref = n0.
 template <typename C>
-__device__ __forceinline__ void collide7(C* g, C Fbar, const Phys<C>& ph) {
+__host__ __device__ __forceinline__ void collide7(C* g, C Fbar, const Phys<C>& ph) {
   const C n0 = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6];
   C n1 = g[1] - g[2], n2 = g[3] - g[4], n3 = g[5] - g[6];
   C n4 = g[1] + g[2] + g[3] + g[4] + g[5] + g[6];
@@ -234,7 +243,7 @@ __device__ __forceinline__ void collide7(C* g, C Fbar, const Phys<C>& ph) {
 // eqs. (27)-(29): c_s^2 dT/dx_a = -varsigma_a m_a (dt = 1) with the
 // pre-collision first moments of g (their equilibrium part is zero).
 template <typename C>
-__device__ __forceinline__ void local_gradT(const C* g, const Phys<C>& ph, C& gx, C& gy, C& gz) {
+__host__ __device__ __forceinline__ void local_gradT(const C* g, const Phys<C>& ph, C& gx, C& gy, C& gz) {
   const C k = div(-ph.vflux, ph.cs2T);
   gx = k * (g[1] - g[2]);
   gy = k * (g[3] - g[4]);
@@ -243,7 +252,7 @@ __device__ __forceinline__ void local_gradT(const C* g, const Phys<C>& ph, C& gx
 
 // eq. (2) deviation: f^eq_i(rho, u) - w_i rho_ref
 template <typename C>
-__device__ __forceinline__ C feq19_dev(int i, C rho, C rho_ref, C ux, C uy, C uz) {
+__host__ __device__ __forceinline__ C feq19_dev(int i, C rho, C rho_ref, C ux, C uy, C uz) {
   const C cu = C(CX[i]) * ux + C(CY[i]) * uy + C(CZ[i]) * uz;
   const C usq = ux * ux + uy * uy + uz * uz;
   return w19<C>(i) * (rho * (C(1) + C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq) - rho_ref);

@@ -14,6 +14,7 @@
 
 #include "kernels_ref.h"
 #include "kernels_fused.h"
+#include "kernels_adjoint.h"
 
 using namespace lbm;
 
@@ -213,43 +214,50 @@ struct Impl {
     return hipGetLastError();
   }
 
-  // S0-S5 on the state A: complete boundary nodes, fill rho, T, psi, u_eq, du.
-  static hipError_t prepass(lbm_ctx* ctx) {
+  // S0-S5 on the state (f, g): complete its boundary nodes in place and fill
+  // rho, T, psi, u_eq, du.
+  static hipError_t prepass_on(lbm_ctx* ctx, S* f, S* g) {
     const lbm_params& p = ctx->p;
     const Geom geo = geom_of(p);
     const Phys<C> ph = phys_of<C>(p);
     const Faces<C> fc = faces_of<C>(ctx);
     const unsigned nb = blocks_for(geo.N);
-    S* fA = (S*)ctx->fA;
-    S* gA = (S*)ctx->gA;
-    hipError_t e = thermal_dirichlet(ctx, gA);
+    hipError_t e = thermal_dirichlet(ctx, g);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_macro<S>, dim3(nb), dim3(256), 0, ctx->stream, fA, gA, (C*)ctx->rho, (C*)ctx->T,
+    hipLaunchKernelGGL(k_macro<S>, dim3(nb), dim3(256), 0, ctx->stream, f, g, (C*)ctx->rho, (C*)ctx->T,
                        (C*)ctx->psi, ctx->flag, geo, fc, ph);
-    hipLaunchKernelGGL(k_force<S>, dim3(nb), dim3(256), 0, ctx->stream, fA, (const C*)ctx->rho,
+    hipLaunchKernelGGL(k_force<S>, dim3(nb), dim3(256), 0, ctx->stream, f, (const C*)ctx->rho,
                        (const C*)ctx->psi, (C*)ctx->ueq, (C*)ctx->du, geo, fc, ph);
     return hipGetLastError();
   }
 
-  static hipError_t step_ref(lbm_ctx* ctx) {
-    hipError_t e = prepass(ctx);
+  static hipError_t prepass(lbm_ctx* ctx) { return prepass_on(ctx, (S*)ctx->fA, (S*)ctx->gA); }
+
+  // One step from the state (fs, gs) into (fd, gd).  The unfused kernels
+  // complete the boundary nodes of (fs, gs) in place; the fused kernel only
+  // reads it.
+  static hipError_t step_ref(lbm_ctx* ctx, S* fs, S* gs, S* fd, S* gd) {
+    hipError_t e = prepass_on(ctx, fs, gs);
     if (e != hipSuccess) return e;
     const Geom geo = geom_of(ctx->p);
-    hipLaunchKernelGGL(k_collide_push<S>, dim3(blocks_for(geo.N)), dim3(256), 0, ctx->stream, (const S*)ctx->fA,
-                       (const S*)ctx->gA, (S*)ctx->fB, (S*)ctx->gB, (const C*)ctx->rho, (const C*)ctx->T,
-                       (const C*)ctx->ueq, (const C*)ctx->du, geo, phys_of<C>(ctx->p));
+    hipLaunchKernelGGL(k_collide_push<S>, dim3(blocks_for(geo.N)), dim3(256), 0, ctx->stream, (const S*)fs,
+                       (const S*)gs, fd, gd, (const C*)ctx->rho, (const C*)ctx->T, (const C*)ctx->ueq,
+                       (const C*)ctx->du, geo, phys_of<C>(ctx->p));
     return hipGetLastError();
   }
 
-  static hipError_t step_fused(lbm_ctx* ctx) {
+  static hipError_t step_fused(lbm_ctx* ctx, const S* fs, const S* gs, S* fd, S* gd) {
     const lbm_params& p = ctx->p;
-    return FusedImpl<S>::step(p, phys_of<C>(p), ctx->stream, (const S*)ctx->fA, (const S*)ctx->gA, (S*)ctx->fB,
-                              (S*)ctx->gB, ctx->has_Tw[0] ? ctx->Tw[0] : nullptr,
+    return FusedImpl<S>::step(p, phys_of<C>(p), ctx->stream, fs, gs, fd, gd, ctx->has_Tw[0] ? ctx->Tw[0] : nullptr,
                               ctx->has_Tw[1] ? ctx->Tw[1] : nullptr, ctx->flag, ctx->fused_chunk);
   }
 
+  static hipError_t step_from(lbm_ctx* ctx, S* fs, S* gs, S* fd, S* gd) {
+    return ctx->fused_ok ? step_fused(ctx, fs, gs, fd, gd) : step_ref(ctx, fs, gs, fd, gd);
+  }
+
   static hipError_t step(lbm_ctx* ctx) {
-    hipError_t e = ctx->fused_ok ? step_fused(ctx) : step_ref(ctx);
+    hipError_t e = step_from(ctx, (S*)ctx->fA, (S*)ctx->gA, (S*)ctx->fB, (S*)ctx->gB);
     if (e != hipSuccess) return e;
     std::swap(ctx->fA, ctx->fB);
     std::swap(ctx->gA, ctx->gB);
@@ -305,6 +313,187 @@ lbm_status reduce_now(lbm_ctx* ctx, double out[RED_VALUES]) {
   HIPCHK(ctx, dispatch(ctx, [&](auto impl) { return decltype(impl)::diag(ctx); }));
   HIPCHK(ctx, hipMemcpyAsync(out, ctx->sums, RED_VALUES * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return LBM_OK;
+}
+
+
+// ------------------------------------------------------------- adjoint
+
+// Memory plan of lbm_adjoint: checkpoints of the state every L steps, one
+// segment of L recomputed states, two copies of the adjoint populations,
+// the adjoint fields and wall planes, the FP64 gradient accumulators.
+struct AdjPlan {
+  int nsteps = 0, nseg = 0, L = 0;
+  size_t fbytes = 0, gbytes = 0;
+  size_t off_ck = 0, off_seg = 0, off_lf[2] = {0, 0}, off_lg[2] = {0, 0}, off_rho = 0, off_T = 0, off_div = 0,
+         off_ueq = 0, off_du = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0, off_acc = 0;
+  size_t total = 0;
+  size_t state() const { return fbytes + gbytes; }
+};
+
+AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp) {
+  AdjPlan a;
+  a.nsteps = sp.nsteps;
+  int K = sp.n_checkpoints > 0 ? sp.n_checkpoints : (int)std::ceil(std::sqrt((double)sp.nsteps));
+  K = std::max(1, std::min(K, sp.nsteps));
+  a.L = (sp.nsteps + K - 1) / K;
+  a.nseg = (sp.nsteps + a.L - 1) / a.L;
+  const size_t N = (size_t)ncells(p);
+  const size_t P = (size_t)p.nx * p.ny;
+  const size_t es = elem_size(p.precision), cs = compute_size(p.precision);
+  a.fbytes = align_up(19 * N * es);
+  a.gbytes = align_up(7 * N * es);
+  size_t o = 0;
+  a.off_ck = o; o += (size_t)a.nseg * a.state();
+  a.off_seg = o; o += (size_t)a.L * a.state();
+  for (int k = 0; k < 2; ++k) {
+    a.off_lf[k] = o; o = align_up(o + 19 * N * cs);
+    a.off_lg[k] = o; o = align_up(o + 7 * N * cs);
+  }
+  a.off_rho = o; o = align_up(o + N * cs);
+  a.off_T = o; o = align_up(o + N * cs);
+  a.off_div = o; o = align_up(o + N * cs);
+  a.off_ueq = o; o = align_up(o + 3 * N * cs);
+  a.off_du = o; o = align_up(o + 3 * N * cs);
+  a.off_gadj = o; o = align_up(o + 2 * P * cs);
+  a.off_ax = o; o = align_up(o + 2 * P * cs);
+  a.off_ay = o; o = align_up(o + 2 * P * cs);
+  a.off_kap = o; o = align_up(o + 2 * P * cs);
+  a.off_grad = o; o = align_up(o + P * 8);
+  a.off_acc = o; o = align_up(o + 64);
+  a.total = o;
+  return a;
+}
+
+lbm_status adjoint_check(const lbm_ctx* ctx, const lbm_adjoint_spec* sp, std::string& msg) {
+  if (!sp) { msg = "spec is NULL"; return LBM_EINVAL; }
+  if (sp->nsteps < 1) { msg = "nsteps must be >= 1"; return LBM_EINVAL; }
+  if (sp->n_checkpoints < 0) { msg = "n_checkpoints must be >= 0"; return LBM_EINVAL; }
+  if (sp->objective != 0) { msg = "unknown objective"; return LBM_EINVAL; }
+  if (sp->wall_face != 4 && sp->wall_face != 5) { msg = "wall_face must be 4 or 5"; return LBM_EINVAL; }
+  if (ctx->p.face[sp->wall_face] == LBM_FACE_PERIODIC) { msg = "wall_face is periodic"; return LBM_EINVAL; }
+  for (int k = 0; k < 4; ++k)
+    if (ctx->p.face[k] != LBM_FACE_PERIODIC) {
+      msg = "the adjoint needs periodic x and y faces"; return LBM_EUNSUPPORTED;
+    }
+  return LBM_OK;
+}
+
+struct DeviceBlock {
+  void* ptr = nullptr;
+  hipStream_t stream = nullptr;
+  ~DeviceBlock() {
+    if (ptr) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipFree(ptr);
+    }
+  }
+};
+
+template <typename S>
+lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, double* dJ_dTw, double* dJ_dkappa,
+                       int32_t on_device) {
+  using C = typename Storage<S>::C;
+  using I = Impl<S>;
+  const lbm_params& p = ctx->p;
+  const AdjPlan a = adjoint_plan(p, sp);
+  const Geom geo = geom_of(p);
+  const long long N = geo.N;
+  const long long P = (long long)p.nx * p.ny;
+  DeviceBlock blk;
+  blk.stream = ctx->stream;
+  {
+    const hipError_t e = hipMalloc(&blk.ptr, a.total);
+    if (e != hipSuccess) {
+      blk.ptr = nullptr;
+      ctx->err = std::string("adjoint workspace of ") + std::to_string(a.total) + " bytes: " + hipGetErrorString(e);
+      return LBM_ENOMEM;
+    }
+  }
+  char* b = (char*)blk.ptr;
+  auto ck_f = [&](int k) { return (S*)(b + a.off_ck + (size_t)k * a.state()); };
+  auto ck_g = [&](int k) { return (S*)(b + a.off_ck + (size_t)k * a.state() + a.fbytes); };
+  auto sg_f = [&](int j) { return (S*)(b + a.off_seg + (size_t)j * a.state()); };
+  auto sg_g = [&](int j) { return (S*)(b + a.off_seg + (size_t)j * a.state() + a.fbytes); };
+  C* lf[2] = {(C*)(b + a.off_lf[0]), (C*)(b + a.off_lf[1])};
+  C* lg[2] = {(C*)(b + a.off_lg[0]), (C*)(b + a.off_lg[1])};
+  C* a_rho = (C*)(b + a.off_rho);
+  C* a_T = (C*)(b + a.off_T);
+  C* a_div = (C*)(b + a.off_div);
+  C* a_ueq = (C*)(b + a.off_ueq);
+  C* a_du = (C*)(b + a.off_du);
+  C* gadj = (C*)(b + a.off_gadj);
+  C* ax = (C*)(b + a.off_ax);
+  C* ay = (C*)(b + a.off_ay);
+  C* kap = (C*)(b + a.off_kap);
+  double* grad = (double*)(b + a.off_grad);
+  double* acc = (double*)(b + a.off_acc);
+  const hipStream_t st = ctx->stream;
+  const size_t fsz = 19 * (size_t)N * sizeof(S), gsz = 7 * (size_t)N * sizeof(S);
+  const bool walls = p.face[4] == LBM_FACE_WALL || p.face[5] == LBM_FACE_WALL;
+
+  // forward pass with checkpoints; J = M(t0) - M(t0 + N)
+  double s0[RED_VALUES], s1[RED_VALUES];
+  lbm_status rs = reduce_now(ctx, s0);
+  if (rs != LBM_OK) return rs;
+  for (int k = 0; k < a.nseg; ++k) {
+    HIPCHK(ctx, hipMemcpyAsync(ck_f(k), ctx->fA, fsz, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(ck_g(k), ctx->gA, gsz, hipMemcpyDeviceToDevice, st));
+    const int len = std::min(a.L, a.nsteps - k * a.L);
+    for (int j = 0; j < len; ++j) {
+      HIPCHK(ctx, I::step(ctx));
+      ctx->step++;
+    }
+  }
+  rs = reduce_now(ctx, s1);
+  if (rs != LBM_OK) return rs;
+  {
+    int flag = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&flag, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (flag) { ctx->err = "non-physical state in the forward pass"; return LBM_ENONPHYS; }
+  }
+
+  // reverse sweep, one segment at a time
+  const Phys<C> ph = phys_of<C>(p);
+  const unsigned nb = blocks_for(N), npb = blocks_for(P);
+  hipLaunchKernelGGL(k_adj_seed<C>, dim3(nb), dim3(256), 0, st, lf[0], lg[0], geo);
+  HIPCHK(ctx, hipMemsetAsync(grad, 0, P * 8, st));
+  HIPCHK(ctx, hipMemsetAsync(acc, 0, 64, st));
+  int cur = 0;
+  for (int k = a.nseg - 1; k >= 0; --k) {
+    const int len = std::min(a.L, a.nsteps - k * a.L);
+    HIPCHK(ctx, hipMemcpyAsync(sg_f(0), ck_f(k), fsz, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(sg_g(0), ck_g(k), gsz, hipMemcpyDeviceToDevice, st));
+    for (int j = 1; j < len; ++j) HIPCHK(ctx, I::step_from(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j)));
+    for (int j = len - 1; j >= 0; --j) {
+      const S* gnext = j + 1 < len ? sg_g(j + 1) : (k + 1 < a.nseg ? ck_g(k + 1) : (const S*)ctx->gA);
+      HIPCHK(ctx, I::prepass_on(ctx, sg_f(j), sg_g(j)));
+      const int nx = 1 - cur;
+      hipLaunchKernelGGL(k_adj_collide<S>, dim3(nb), dim3(256), 0, st, (const C*)lf[cur], (const C*)lg[cur],
+                         (const S*)sg_g(j), gnext, (const C*)ctx->rho, (const C*)ctx->T, (const C*)ctx->ueq,
+                         (const C*)ctx->du, lf[nx], lg[nx], a_rho, a_T, a_ueq, a_du, a_div, geo, ph);
+      hipLaunchKernelGGL(k_adj_velocity<C>, dim3(nb), dim3(256), 0, st, lf[nx], (const C*)a_div, a_ueq, a_du,
+                         a_rho, (const C*)ctx->rho, (const C*)ctx->ueq, (const C*)ctx->du, geo);
+      if (walls)
+        hipLaunchKernelGGL(k_adj_ghost<C>, dim3(npb), dim3(256), 0, st, (const C*)a_du, (const C*)ctx->psi, gadj, ax,
+                           ay, kap, geo, ph);
+      hipLaunchKernelGGL(k_adj_psi<C>, dim3(nb), dim3(256), 0, st, lf[nx], lg[nx], (const C*)a_rho,
+                         (const C*)a_T, (const C*)a_ueq, (const C*)a_du, (const C*)ctx->psi, (const C*)ctx->rho,
+                         (const C*)ctx->T, (const C*)gadj, (const C*)ax, (const C*)ay, geo, ph);
+      hipLaunchKernelGGL(k_adj_dirichlet<C>, dim3(npb), dim3(256), 0, st, lg[nx], grad, (int)sp.wall_face, geo, ph);
+      if (walls) hipLaunchKernelGGL(k_accumulate<C>, dim3(1), dim3(RED_THREADS), 0, st, (const C*)kap, 2 * P, acc);
+      HIPCHK(ctx, hipGetLastError());
+      cur = nx;
+    }
+  }
+  double kappa_grad = 0.0;
+  HIPCHK(ctx, hipMemcpyAsync(&kappa_grad, acc, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (dJ_dTw)
+    HIPCHK(ctx, hipMemcpyAsync(dJ_dTw, grad, P * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  if (J) *J = s0[0] - s1[0];
+  if (dJ_dkappa) *dJ_dkappa = kappa_grad;
   return LBM_OK;
 }
 
@@ -541,6 +730,29 @@ lbm_status lbm_reduce(lbm_ctx* ctx, lbm_diag* out) {
   out->evap_mass = ctx->mass0 - sums[0];
   out->step = ctx->step;
   return LBM_OK;
+}
+
+lbm_status lbm_adjoint_bytes(const lbm_ctx* ctx, const lbm_adjoint_spec* spec, size_t* bytes) {
+  if (!ctx || !bytes) return LBM_EINVAL;
+  std::string msg;
+  const lbm_status s = adjoint_check(ctx, spec, msg);
+  if (s != LBM_OK) return s;
+  *bytes = adjoint_plan(ctx->p, *spec).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint(lbm_ctx* ctx, const lbm_adjoint_spec* spec, double* J, double* dJ_dTw, double* dJ_dkappa,
+                       int32_t dst_on_device) {
+  if (!ctx) return LBM_EINVAL;
+  const lbm_status s = adjoint_check(ctx, spec, ctx->err);
+  if (s != LBM_OK) return s;
+  if (!ctx->initialised) { ctx->err = "lbm_adjoint before lbm_init"; return LBM_ESTATE; }
+  switch (ctx->p.precision) {
+    case LBM_FP64: return adjoint_run<double>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device);
+    case LBM_FP32_DEV: return adjoint_run<float>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device);
+    case LBM_FP16_DEV: return adjoint_run<_Float16>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device);
+    default: return adjoint_run<bf16>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device);
+  }
 }
 
 const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }

@@ -48,9 +48,14 @@ class LbmDiag(ctypes.Structure):
                 ("vol_smooth", ctypes.c_double), ("evap_mass", ctypes.c_double), ("step", ctypes.c_int64)]
 
 
+class LbmAdjointSpec(ctypes.Structure):
+    _fields_ = [("nsteps", ctypes.c_int32), ("n_checkpoints", ctypes.c_int32), ("objective", ctypes.c_int32),
+                ("wall_face", ctypes.c_int32)]
+
+
 EXPORTS = ["lbm_default_params", "lbm_required_bytes", "lbm_create", "lbm_init", "lbm_set_wall_T",
-           "lbm_set_kappa", "lbm_step", "lbm_fields", "lbm_populations", "lbm_reduce", "lbm_last_error",
-           "lbm_destroy"]
+           "lbm_set_kappa", "lbm_step", "lbm_fields", "lbm_populations", "lbm_reduce", "lbm_adjoint_bytes",
+           "lbm_adjoint", "lbm_last_error", "lbm_destroy"]
 
 _lib = None
 
@@ -79,6 +84,8 @@ def load_library():
     lib.lbm_fields.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     lib.lbm_populations.argtypes = [ctypes.c_void_p, dp, dp]
     lib.lbm_reduce.argtypes = [ctypes.c_void_p, P(LbmDiag)]
+    lib.lbm_adjoint_bytes.argtypes = [ctypes.c_void_p, P(LbmAdjointSpec), P(ctypes.c_size_t)]
+    lib.lbm_adjoint.argtypes = [ctypes.c_void_p, P(LbmAdjointSpec), dp, ctypes.c_void_p, dp, ctypes.c_int32]
     lib.lbm_last_error.argtypes = [ctypes.c_void_p]
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_destroy.argtypes = [ctypes.c_void_p]
@@ -238,6 +245,23 @@ class Lbm3D:
         return dict(mass=d.mass, energy=d.energy, vol_hard=d.vol_hard, vol_smooth=d.vol_smooth,
                     evap_mass=d.evap_mass, step=d.step)
 
+    def adjoint_bytes(self, nsteps: int, wall_face: int = 4, n_checkpoints: int = 0) -> int:
+        spec = LbmAdjointSpec(int(nsteps), int(n_checkpoints), 0, int(wall_face))
+        n = ctypes.c_size_t()
+        self._check(self.lib.lbm_adjoint_bytes(self.ctx, ctypes.byref(spec), ctypes.byref(n)), self.ctx)
+        return n.value
+
+    def adjoint(self, nsteps: int, wall_face: int = 4, n_checkpoints: int = 0):
+        """Advance nsteps and return (J, dJ/dT_w as (ny, nx), dJ/dkappa_w) for the
+        evaporated mass J = M(t0) - M(t0 + nsteps)."""
+        spec = LbmAdjointSpec(int(nsteps), int(n_checkpoints), 0, int(wall_face))
+        J = ctypes.c_double()
+        dk = ctypes.c_double()
+        grad = np.empty(self.params.nx * self.params.ny)
+        self._check(self.lib.lbm_adjoint(self.ctx, ctypes.byref(spec), ctypes.byref(J), grad.ctypes.data,
+                                         ctypes.byref(dk), 0), self.ctx)
+        return J.value, grad.reshape(self.params.ny, self.params.nx), dk.value
+
 
 def from_workload(w: Dict, precision="fp32", device="cuda") -> Lbm3D:
     sim = Lbm3D(params_from_workload(w, precision), device=device)
@@ -245,3 +269,32 @@ def from_workload(w: Dict, precision="fp32", device="cuda") -> Lbm3D:
     for face, field in (w.get("Tw") or {}).items():
         sim.set_wall_T(face, field)
     return sim
+
+
+def evaporated_mass_function():
+    """torch.autograd.Function: J = EvaporatedMass.apply(sim, rho0, T0, nsteps, face, Tw, kappa).
+
+    Tw: float64 tensor (ny, nx) of wall temperatures; kappa: float64 scalar
+    tensor.  The forward pass runs lbm_adjoint once (the discrete adjoint
+    needs the forward trajectory anyway) and keeps the gradients; backward
+    scales them by the incoming gradient.  rho0, T0 (numpy) fix the state
+    the simulation restarts from on every call."""
+    import torch
+
+    class EvaporatedMass(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sim, rho0, T0, nsteps, face, Tw, kappa):
+            sim.init(rho0, T0)
+            sim.set_wall_T(face, Tw.detach().cpu().numpy().astype(np.float64))
+            sim.set_kappa(float(kappa))
+            J, dTw, dk = sim.adjoint(int(nsteps), wall_face=int(face))
+            ctx.save_for_backward(torch.as_tensor(dTw, dtype=torch.float64, device=Tw.device),
+                                  torch.tensor(dk, dtype=torch.float64, device=kappa.device))
+            return torch.tensor(J, dtype=torch.float64, device=Tw.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            dTw, dk = ctx.saved_tensors
+            return None, None, None, None, None, gJ * dTw, gJ * dk
+
+    return EvaporatedMass

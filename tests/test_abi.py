@@ -48,18 +48,22 @@ def test_struct_layout_matches_header(tmp_path):
     body = "\n".join(f'  printf("%zu\\n", offsetof(lbm_params, {c}));' for c in cfields)
     dfields = [f[0] for f in P.lbm3d.LbmDiag._fields_]
     dbody = "\n".join(f'  printf("%zu\\n", offsetof(lbm_diag, {c}));' for c in dfields)
+    afields = [f[0] for f in P.lbm3d.LbmAdjointSpec._fields_]
+    abody = '  printf("%zu\\n", sizeof(lbm_adjoint_spec));\n' + "\n".join(
+        f'  printf("%zu\\n", offsetof(lbm_adjoint_spec, {c}));' for c in afields)
     src.write_text(textwrap.dedent("""
         #include <stdio.h>
         #include <stddef.h>
         #include "lbm3d.h"
         int main(void) {
           printf("%zu\\n", sizeof(lbm_params));
-        """) + body + '\n  printf("%zu\\n", sizeof(lbm_diag));\n' + dbody + "\n  return 0;\n}\n")
+        """) + body + '\n  printf("%zu\\n", sizeof(lbm_diag));\n' + dbody + "\n" + abody + "\n  return 0;\n}\n")
     exe = tmp_path / "probe"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     expect = [ctypes.sizeof(P.LbmParams)] + [getattr(P.LbmParams, f).offset for f in fields]
     expect += [ctypes.sizeof(P.lbm3d.LbmDiag)] + [getattr(P.lbm3d.LbmDiag, f).offset for f in dfields]
+    expect += [ctypes.sizeof(P.lbm3d.LbmAdjointSpec)] + [getattr(P.lbm3d.LbmAdjointSpec, f).offset for f in afields]
     assert vals == expect
 
 
