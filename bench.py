@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--variant-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--adjoint-workload", default="heated_wall_adjoint_96",
+                    help="workload of the adjoint timing ('' to skip)")
+    ap.add_argument("--adjoint-precisions", default="fp64,fp32")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this size 3 times (HBM counter calibration)")
     return ap.parse_args()
@@ -92,11 +95,46 @@ def time_precision(P, torch, w, prec, steps, warmup):
                 frac=achieved / PEAK_HBM_GBS, mass=diag["mass"])
 
 
+def time_adjoint(P, torch, w, prec):
+    """Cost of the gradient of the evaporated mass over the workload's steps:
+    N forward steps alone, then lbm_adjoint (forward pass with checkpoints,
+    segment recomputation, reverse sweep)."""
+    import math
+    n = w["steps"]
+    sim = P.from_workload(w, precision=prec)
+    sim.step(2)
+    stream = sim.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    sim.init(w["rho0"], w["T0"])
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    sim.step(n)
+    ev[1].record(stream)
+    sim.init(w["rho0"], w["T0"])
+    torch.cuda.synchronize()
+    ev[2].record(stream)
+    J, grad, dk = sim.adjoint(n, wall_face=4)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1]) * 1e-3
+    tot = ev[2].elapsed_time(ev[3]) * 1e-3
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    k = math.ceil(math.sqrt(n))
+    seg = -(-n // -(-n // k))
+    recompute = (n - seg) / n
+    return dict(forward_ms_per_step=round(fwd / n * 1e3, 4), gradient_s=round(tot, 3),
+                gradient_over_forward=round(tot / fwd, 3),
+                adjoint_step_over_forward_step=round(tot / fwd - 1.0 - recompute, 3),
+                J=J, dJ_dkappa=dk)
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle (unchanged, single-threaded numpy) on a bounded sample of
-    the workload: the same closed-box recipe (walls at 0.80 and 0.95 Tc,
-    linear initial T, seeded blobs) at 64 x 64 x 48 with 4 blobs of radius
-    5-9, so that it stays a physical state."""
+    the workload: the same closed-box recipe (walls at 0.85 and 0.95 Tc,
+    linear initial T, seeded non-overlapping blobs) at 64 x 64 x 48 with 4
+    blobs of radius 5-9."""
     from threadpoolctl import threadpool_limits
     from oracle import lbm_oracle as O
     from workloads import synth
@@ -149,6 +187,14 @@ def main():
         r = time_precision(P, torch, w, prec, vsteps, max(2, args.warmup // 2))
         variants[prec] = dict(mlups=round(r["mlups"], 1), ms_per_step=round(r["ms_per_step"], 4),
                               alg_bytes_per_cell=ALG_BYTES[prec], roofline_frac=round(r["frac"], 4))
+    adjoint = None
+    if args.adjoint_workload:
+        wa = synth.named(args.adjoint_workload)
+        adjoint = {"workload": args.adjoint_workload, "grid": [wa["nx"], wa["ny"], wa["nz"]], "steps": wa["steps"],
+                   "objective": "evaporated mass M(0)-M(N)", "checkpoints": "ceil(sqrt(N))"}
+        for prec in [v for v in args.adjoint_precisions.split(",") if v]:
+            print(f"[bench] adjoint {prec} on {args.adjoint_workload}", file=sys.stderr, flush=True)
+            adjoint[prec] = time_adjoint(P, torch, wa, prec)
     traffic = measured_traffic(args.workload, args.precision, cells)
     out = {
         "metric": "coupled D3Q19+D3Q7 MLUPS & % HBM roofline",
@@ -169,6 +215,7 @@ def main():
                      "unit": "GB/s", "frac": round(head["frac"], 4), "traffic": traffic,
                      "alg_bytes_per_cell": ALG_BYTES[args.precision]},
         "variants": variants,
+        "adjoint": adjoint,
         "source_hash": source_hash(),
     }
     if not args.no_cpu_baseline:

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import lbm_oracle as O
+from workloads import synth
 
 RNG = np.random.default_rng(12345)
 
@@ -556,3 +557,19 @@ def test_splitmix64_reference_vector():
     from workloads import synth
     z = synth.splitmix64(0, 3)
     assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+@pytest.mark.slow
+def test_flat_interface_coexistence_oracle():
+    """Flat liquid slab on the oracle (1-D column, T held by a very large
+    c_v): bulk densities near the Maxwell construction.  Loose: pseudopotential
+    coexistence is not Maxwell-consistent (converged: liquid -0.2 %, vapour
+    -16 %)."""
+    w = synth.slab(nx=128, ny=1, nz=1, width=64.0)
+    p = O.Params(w["nx"], w["ny"], w["nz"], cv=1e6)
+    f, g = O.init_populations(w["rho0"], w["T0"], p)
+    f, g = O.run(f, g, p, 15000)
+    rho, u, _ = O.fields(f, g, p)
+    assert abs(rho[0, 0, 64] / w["rho_l"] - 1) < 0.01
+    assert abs(rho[0, 0, 0] / w["rho_v"] - 1) < 0.2
+    assert np.max(np.abs(u)) < 1e-6

@@ -160,6 +160,17 @@ def heated_wall(n=256, R0=40.0, W=5.0, Tsat=0.86, Tw_factor=1.15, steps=10000,
     return w
 
 
+def slab(nx=128, ny=8, nz=8, width=64.0, W=5.0, Tsat=0.86, steps=20000):
+    """Flat liquid slab across x in a periodic box at uniform T = Tsat*Tc:
+    liquid for |x - nx/2| < width/2, tanh interfaces of width W."""
+    w = _base("slab", nx, ny, nz, [PERIODIC] * 6, steps, Tsat)
+    z, y, x = _grid(nx, ny, nz)
+    d = np.abs(x - nx / 2) + 0.0 * (y + z)
+    w["rho0"] = tanh_profile(d, width / 2, W, w["rho_l"], w["rho_v"])
+    w["T0"] = np.full(w["rho0"].shape, Tsat * w["Tc"])
+    return w
+
+
 def _poisson(lam: float, u: float) -> int:
     """Inverse-CDF Poisson draw from one uniform number."""
     k = 0
