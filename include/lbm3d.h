@@ -77,13 +77,22 @@ typedef struct {
   double lambda;                 /* thermal conductivity (sets varsigma_1..3)   */
   double cv;                     /* specific heat at constant volume            */
   double s_T_other;              /* varsigma_0 and varsigma_4..6                */
-  int32_t theta_corr;            /* correction term S_i of eq. (16): 0 only     */
+  int32_t theta_corr;            /* vartheta of eq. (13): 0, or 1 for the correction S_i of
+                                  * eq. (16) with d2T/dt2 = T(t) - 2T(t-1) + T(t-2) (applied
+                                  * from the third step after lbm_init; unfused kernels) */
   int32_t face[6];               /* lbm_face_kind per face                      */
   double face_T[6];              /* Dirichlet temperature of each bounded face  */
   double face_rho[6];            /* outlet density of each PRESSURE face        */
   double kappa_w;                /* tan(pi/2 - theta) of eq. (37) on wall faces */
   double rho_ref, T_ref;         /* deviation-storage references               */
   double diag_rho_v, diag_rho_l; /* densities used by the liquid-volume diagnostics */
+  /* Density-dependent conductivity (the liquid and vapour values of the
+   * Sec. 4.1 benchmark): with lambda_vapour > 0 and lambda_liquid > 0,
+   * lambda(rho) is linear in rho between (lambda_rho_v, lambda_vapour) and
+   * (lambda_rho_l, lambda_liquid) and constant beyond, and varsigma_1..3 are
+   * set per node from it; with both 0, lambda is uniform. */
+  double lambda_vapour, lambda_liquid;
+  double lambda_rho_v, lambda_rho_l;
 } lbm_params;
 
 typedef struct {
@@ -113,7 +122,7 @@ lbm_status lbm_required_bytes(const lbm_params* p, size_t* state_bytes, size_t* 
  * device allocation of at least state_bytes + scratch_bytes that must outlive
  * the context.  hip_stream: a hipStream_t, or NULL for the default stream.
  * Parameters are validated (LBM_EINVAL) and unsupported combinations
- * (theta_corr != 0, walls on x/y faces) give LBM_EUNSUPPORTED. */
+ * (walls on x/y faces) give LBM_EUNSUPPORTED. */
 lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_bytes,
                       void* hip_stream, lbm_ctx** out);
 

@@ -188,6 +188,15 @@ class Params:
     face_T: Sequence[float] = (0.0,) * 6
     face_rho: Sequence[float] = (0.0,) * 6
     kappa_w: float = 0.0                 # tan(pi/2 - theta), eq. (37)
+    # Density-dependent conductivity (the Sec. 4.1 benchmark gives liquid and
+    # vapour values): lambda(rho) linear in rho between (lam_rho_v, lam_vapour)
+    # and (lam_rho_l, lam_liquid), constant beyond; None keeps lam uniform.
+    lam_vapour: Optional[float] = None
+    lam_liquid: Optional[float] = None
+    lam_rho_v: float = 0.0
+    lam_rho_l: float = 1.0
+    # vartheta of eq. (13): 1 adds the correction S_i of eq. (16)
+    theta_corr: int = 0
 
     @property
     def shape(self):
@@ -211,6 +220,22 @@ class Params:
         s = self.varsigma_flux
         o = self.s_T_other
         return np.array([o, s, s, s, o, o, o])
+
+    def conductivity(self, rho):
+        """lambda at density rho (uniform lam unless liquid/vapour values are set)."""
+        if self.lam_vapour is None:
+            return np.full(np.shape(rho), self.lam)
+        frac = np.clip((np.real(rho) - self.lam_rho_v) / (self.lam_rho_l - self.lam_rho_v), 0.0, 1.0)
+        return self.lam_vapour + (self.lam_liquid - self.lam_vapour) * frac
+
+    def lambda7_field(self, rho) -> np.ndarray:
+        """Relaxation rates of the D3Q7 collision at every node, (7,) + shape:
+        varsigma_{1,2,3} = 1 / (1/2 + lambda(rho) / c_s^2), the rest s_T_other."""
+        flux = 1.0 / (0.5 + self.conductivity(rho) / self.cs2_T)
+        out = np.empty((7,) + np.shape(rho))
+        out[:] = self.s_T_other
+        out[1:4] = flux
+        return out
 
 
 # --------------------------------------------------------------------------
@@ -653,8 +678,8 @@ def macroscopic(f, g, p: Params, Tw=None):
         ueq = np.where(wall, -0.5 * du, ueq)
     div_u = divergence(u, p)                                    # S6, isotropic stencil
     mg = np.tensordot(C7.T.astype(np.float64), g, axes=(1, 0))  # first moments of g
-    lam7 = p.lambda7()
-    gradT = -(lam7[1:4].reshape(3, 1, 1, 1) * mg) / p.cs2_T     # eqs. (27)-(29)
+    lam7 = p.lambda7_field(rho)
+    gradT = -(lam7[1:4] * mg) / p.cs2_T                         # eqs. (27)-(29)
     dpdT = pr_dp_dT(rho, T, p)
     Fbar = rho * p.cv * np.sum(u * gradT, axis=0) + T * dpdT * div_u   # eq. (15)
     return dict(f=f, g=g, rho=rho, T=T, psi=psi, F=F, j=j, ueq=ueq, du=du, u=u,
@@ -673,17 +698,17 @@ def collide19(f, rho, ueq, du, p: Params):
     return (MHAT_INV @ mstar).reshape(shp)
 
 
-def collide7(g, T, Fbar, p: Params):
+def collide7(g, T, Fbar, p: Params, rho):
     """eq. (13) collision part with theta = 0: g* = g - M^-1 L M (g - g_eq) + dt Fbar_i,
     Fbar_i = -w_i Fbar (eq. (15)); the D3Q7 equilibrium moments are
-    (T, 0, 0, 0, wbar T, 0, 0) (eq. (25))."""
+    (T, 0, 0, 0, wbar T, 0, 0) (eq. (25)); L from the conductivity at rho."""
     shp = g.shape
     n = M7_F @ g.reshape(7, -1)
     Tf = T.reshape(-1)
     neq = np.zeros_like(n)
     neq[0] = Tf
     neq[4] = p.wbar * Tf
-    nstar = n - p.lambda7()[:, None] * (n - neq)
+    nstar = n - p.lambda7_field(rho).reshape(7, -1) * (n - neq)
     gstar = M7_INV @ nstar - w7(p.wbar)[:, None] * Fbar.reshape(-1)[None, :]
     return gstar.reshape(shp)
 
@@ -740,21 +765,40 @@ def stream7_blend(gstar, g, rho, p: Params):
     return out
 
 
-def step(f, g, p: Params, Tw=None):
-    """One full time step S0..S10.  Returns (f_next, g_next, macroscopic dict at t)."""
+def correction_source(mac, p: Params, T_hist):
+    """eq. (16) with vartheta = 1: S_i = w_i rho c_v (dt/2) d^2T/dt^2 enters
+    the collision like the source of eq. (15), so it is applied as Fbar ->
+    Fbar - (1/2) rho c_v d^2T/dt^2.  d^2T/dt^2 is the backward difference
+    T(t) - 2 T(t-1) + T(t-2) of the S1 temperatures (the paper asks for a
+    finite difference without fixing it); zero until two past values exist."""
+    if not p.theta_corr or T_hist is None or len(T_hist) < 2:
+        return mac["Fbar"]
+    d2T = mac["T"] - 2.0 * T_hist[0] + T_hist[1]
+    return mac["Fbar"] - 0.5 * mac["rho"] * p.cv * d2T
+
+
+def step(f, g, p: Params, Tw=None, T_hist=None):
+    """One full time step S0..S10.  T_hist: the S1 temperatures of the two
+    previous steps, most recent first (used with vartheta = 1 only).
+    Returns (f_next, g_next, macroscopic dict at t)."""
     mac = macroscopic(f, g, p, Tw)
+    Fbar = correction_source(mac, p, T_hist)
     fstar = collide19(mac["f"], mac["rho"], mac["ueq"], mac["du"], p)   # S7
-    gstar = collide7(mac["g"], mac["T"], mac["Fbar"], p)                # S8
+    gstar = collide7(mac["g"], mac["T"], Fbar, p, mac["rho"])           # S8
     f_next = stream19(fstar, p)                                         # S9
     g_next = stream7_blend(gstar, mac["g"], mac["rho"], p)              # S10
     return f_next, g_next, mac
 
 
-def run(f, g, p: Params, nsteps: int, Tw=None):
+def run(f, g, p: Params, nsteps: int, Tw=None, T_hist=None):
+    """nsteps steps; T_hist (a list, most recent first) carries the
+    temperature history between calls when vartheta = 1."""
+    hist = T_hist if T_hist is not None else []
     for _ in range(nsteps):
-        f, g, mac = step(f, g, p, Tw)
+        f, g, mac = step(f, g, p, Tw, hist)
         if mac["bad"].any():
             raise FloatingPointError("non-physical state")
+        hist[:] = [mac["T"]] + hist[:1]
     return f, g
 
 

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int i = 0; i < 7; ++i) gp[i] = Storage<S>::load(gA + pidx(g, 7, i, x, y, z));
   C gx, gy, gz;
-  local_gradT(gp, ph, gx, gy, gz);
+  local_gradT(gp, ph.vflux, ph, gx, gy, gz);
   const C rux = ux + C(0.5) * dux, ruy = uy + C(0.5) * duy, ruz = uz + C(0.5) * duz;
   C div = C(0);
 #pragma unroll

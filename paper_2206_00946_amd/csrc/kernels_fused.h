@@ -453,10 +453,12 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       if (has_ring) {
         C Fx, Fy, Fz;
         force_at(re, Fx, Fy, Fz);
-        const C hir = C(0.5) * rcp(s_rho[rq][re]);
-        C vx = s_ueq[sq][0][re] + Fx * hir;
-        C vy = s_ueq[sq][1][re] + Fy * hir;
-        C vz = s_ueq[sq][2][re] + Fz * hir;
+        // same operation order as the tile's own u, so that u does not
+        // depend on which thread evaluates it
+        const C ir = rcp(s_rho[rq][re]);
+        C vx = s_ueq[sq][0][re] + C(0.5) * (Fx * ir);
+        C vy = s_ueq[sq][1][re] + C(0.5) * (Fy * ir);
+        C vz = s_ueq[sq][2][re] + C(0.5) * (Fz * ir);
         if (wall_plane) vx = vy = vz = C(0);
         s_u[0][re] = vx;
         s_u[1][re] = vy;
@@ -483,12 +485,13 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     const bool do_g = ST || (r_exists && r >= z0 && r < z1);
     if (do_g) {
       const C T = ph.T_ref + (ga[0] + ga[1] + ga[2] + ga[3] + ga[4] + ga[5] + ga[6]);
-      C gx, gy, gz;
-      local_gradT(ga, ph, gx, gy, gz);
       const C rho = rho_a;
+      const C vf = vflux_at(rho, ph);
+      C gx, gy, gz;
+      local_gradT(ga, vf, ph, gx, gy, gz);
       const C Fbar = rho * ph.cv * (ua[0] * gx + ua[1] * gy + ua[2] * gz) + T * pr_dpdT(rho, T, ph) * d0;
       const C og0 = ga[0];
-      collide7(ga, Fbar, ph);
+      collide7(ga, Fbar, vf, ph);
       st_at(gB + PS * 7 * zr, G7, colb, 0u, og0 + (ga[0] - og0) * (inv_cv * rcp(rho)));
       // +z: destination is plane r+1 of this column (old value in gb)
       {

@@ -345,7 +345,9 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
                                                       const typename Storage<S>::C* __restrict__ rho_f,
                                                       const typename Storage<S>::C* __restrict__ T_f,
                                                       const typename Storage<S>::C* __restrict__ ueq,
-                                                      const typename Storage<S>::C* __restrict__ du, Geom g,
+                                                      const typename Storage<S>::C* __restrict__ du,
+                                                      const typename Storage<S>::C* __restrict__ Th1,
+                                                      typename Storage<S>::C* __restrict__ Th2, int corr, Geom g,
                                                       Phys<typename Storage<S>::C> ph) {
   using C = typename Storage<S>::C;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -369,15 +371,23 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
   C gp[7];
 #pragma unroll
   for (int i = 0; i < 7; ++i) gp[i] = Storage<S>::load(gA + pidx(g, 7, i, x, y, z));
+  const C vf = vflux_at(rho, ph);
   C gx, gy, gz;
-  local_gradT(gp, ph, gx, gy, gz);
+  local_gradT(gp, vf, ph, gx, gy, gz);
   const C rux = ux + C(0.5) * dux, ruy = uy + C(0.5) * duy, ruz = uz + C(0.5) * duz;
-  const C Fbar = rho * ph.cv * (rux * gx + ruy * gy + ruz * gz) + T * pr_dpdT(rho, T, ph) * div;
+  C Fbar = rho * ph.cv * (rux * gx + ruy * gy + ruz * gz) + T * pr_dpdT(rho, T, ph) * div;
+  if (corr) {
+    // eq. (16), vartheta = 1: S_i = w_i rho c_v (dt/2) d2T/dt2 with the
+    // backward difference T(t) - 2 T(t-1) + T(t-2); Th1 holds T(t-1), Th2
+    // holds T(t-2) and receives T(t)
+    if (corr == 2) Fbar -= C(0.5) * rho * ph.cv * (T - C(2) * Th1[c] + Th2[c]);
+    Th2[c] = T;
+  }
   C f[19];
 #pragma unroll
   for (int i = 0; i < 19; ++i) f[i] = Storage<S>::load(fA + pidx(g, 19, i, x, y, z));
   collide19(f, rho, rho - ph.rho_ref, ux, uy, uz, dux, duy, duz, ph);
-  collide7(gp, Fbar, ph);
+  collide7(gp, Fbar, vf, ph);
   // push streaming, eq. (9); links leaving through a wall bounce back (eq. (34))
 #pragma unroll
   for (int i = 0; i < 19; ++i) {

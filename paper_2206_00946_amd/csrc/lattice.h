@@ -39,7 +39,20 @@ struct Phys {
   C kappa_w;                  // eq. (37)
   C rho_ref, T_ref;           // deviation references
   C inv_b;
+  int var_lambda;             // 1: conductivity linear in rho between the two phases
+  C lam_v, lam_l, lam_rv, lam_inv_drho;
 };
+
+// varsigma_{1,2,3} of the D3Q7 collision at density rho: 1 / (1/2 + lambda / c_s^2),
+// lambda uniform or linear in rho between the vapour and liquid values
+template <typename C>
+__host__ __device__ __forceinline__ C vflux_at(C rho, const Phys<C>& ph) {
+  if (!ph.var_lambda) return ph.vflux;
+  C fr = (rho - ph.lam_rv) * ph.lam_inv_drho;
+  fr = fr < C(0) ? C(0) : (fr > C(1) ? C(1) : fr);
+  const C lam = ph.lam_v + (ph.lam_l - ph.lam_v) * fr;
+  return C(1) / (C(0.5) + lam / ph.cs2T);
+}
 
 // ---------------------------------------------------------------- arithmetic
 // FP32 uses the hardware reciprocal and square root (about 1 ulp); FP64 keeps
@@ -212,16 +225,17 @@ __host__ __device__ __forceinline__ void collide19(C* f, C rho, C rt, C ux, C uy
 // ---------------------------------------------------------------- D3Q7
 // Collision of eq. (13) with the D3Q7 transform (A.2) and theta = 0, on
 // deviations: n = M gt, n* = n - L (n - (Tt, 0, 0, 0, wbar Tt, 0, 0)),
+// varsigma_{1,2,3} = vflux (the node's conductivity),
 // gt* = M^-1 n* - w_i Fbar (source of eq. (15)).  Tt = T - T_ref = n0.
 template <typename C>
-__host__ __device__ __forceinline__ void collide7(C* g, C Fbar, const Phys<C>& ph) {
+__host__ __device__ __forceinline__ void collide7(C* g, C Fbar, C vflux, const Phys<C>& ph) {
   const C n0 = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6];
   C n1 = g[1] - g[2], n2 = g[3] - g[4], n3 = g[5] - g[6];
   C n4 = g[1] + g[2] + g[3] + g[4] + g[5] + g[6];
   C n5 = g[1] + g[2] - g[3] - g[4];
   C n6 = g[1] + g[2] - g[5] - g[6];
   const C om = C(1) - ph.vother;
-  const C of = C(1) - ph.vflux;
+  const C of = C(1) - vflux;
   n1 *= of;
   n2 *= of;
   n3 *= of;
@@ -243,8 +257,9 @@ __host__ __device__ __forceinline__ void collide7(C* g, C Fbar, const Phys<C>& p
 // eqs. (27)-(29): c_s^2 dT/dx_a = -varsigma_a m_a (dt = 1) with the
 // pre-collision first moments of g (their equilibrium part is zero).
 template <typename C>
-__host__ __device__ __forceinline__ void local_gradT(const C* g, const Phys<C>& ph, C& gx, C& gy, C& gz) {
-  const C k = div(-ph.vflux, ph.cs2T);
+__host__ __device__ __forceinline__ void local_gradT(const C* g, C vflux, const Phys<C>& ph, C& gx, C& gy,
+                                                     C& gz) {
+  const C k = div(-vflux, ph.cs2T);
   gx = k * (g[1] - g[2]);
   gy = k * (g[3] - g[4]);
   gz = k * (g[5] - g[6]);

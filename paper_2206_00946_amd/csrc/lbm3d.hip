@@ -55,6 +55,8 @@ struct lbm_ctx {
   void* psi = nullptr;
   void* ueq = nullptr;
   void* du = nullptr;
+  void* Th[2] = {nullptr, nullptr};  // S1 temperatures of the last two steps (vartheta = 1)
+  int hist = 0;                      // how many of them are valid
   double* Tw[2] = {nullptr, nullptr};
   bool has_Tw[2] = {false, false};
   double* partials = nullptr;
@@ -75,8 +77,8 @@ long long ncells(const lbm_params& p) { return (long long)p.nx * p.ny * p.nz; }
 
 struct Layout {
   size_t state = 0, scratch = 0;
-  size_t off_fA, off_gA, off_fB, off_gB, off_rho, off_T, off_psi, off_ueq, off_du, off_Tw0, off_Tw1, off_part,
-      off_sums, off_flag, off_stage;
+  size_t off_fA, off_gA, off_fB, off_gB, off_rho, off_T, off_psi, off_ueq, off_du, off_Th0, off_Th1, off_Tw0, off_Tw1,
+      off_part, off_sums, off_flag, off_stage;
 };
 
 Layout layout_of(const lbm_params& p) {
@@ -94,6 +96,9 @@ Layout layout_of(const lbm_params& p) {
   L.off_psi = o; o = align_up(o + N * cs);
   L.off_ueq = o; o = align_up(o + 3 * N * cs);
   L.off_du = o; o = align_up(o + 3 * N * cs);
+  const size_t nh = p.theta_corr ? N : 0;  // temperature history for vartheta = 1
+  L.off_Th0 = o; o = align_up(o + nh * cs);
+  L.off_Th1 = o; o = align_up(o + nh * cs);
   L.off_Tw0 = o; o = align_up(o + (size_t)p.nx * p.ny * 8);
   L.off_Tw1 = o; o = align_up(o + (size_t)p.nx * p.ny * 8);
   L.off_part = o; o = align_up(o + RED_BLOCKS * RED_VALUES * 8);
@@ -137,7 +142,13 @@ lbm_status validate(const lbm_params* p, std::string& msg) {
       msg = "pressure faces need 0 < face_rho < 1/b"; return LBM_EINVAL;
     }
   }
-  if (p->theta_corr != 0) { msg = "the correction term S_i (theta = 1) is not implemented"; return LBM_EUNSUPPORTED; }
+  if (p->lambda_vapour != 0.0 || p->lambda_liquid != 0.0) {
+    if (!(p->lambda_vapour > 0 && p->lambda_liquid > 0 && p->lambda_rho_l > p->lambda_rho_v)) {
+      msg = "density-dependent conductivity needs lambda_vapour, lambda_liquid > 0 and lambda_rho_l > lambda_rho_v";
+      return LBM_EINVAL;
+    }
+  }
+  if (p->theta_corr != 0 && p->theta_corr != 1) { msg = "theta_corr must be 0 or 1"; return LBM_EINVAL; }
   for (int k = 0; k < 4; ++k)
     if (p->face[k] == LBM_FACE_WALL) { msg = "walls are supported on the z faces only"; return LBM_EUNSUPPORTED; }
   if ((p->face[4] == LBM_FACE_WALL || p->face[5] == LBM_FACE_WALL))
@@ -162,6 +173,11 @@ Phys<C> phys_of(const lbm_params& p) {
   ph.rho_ref = (C)p.rho_ref;
   ph.T_ref = (C)p.T_ref;
   ph.inv_b = (C)(1.0 / p.b);
+  ph.var_lambda = p.lambda_vapour > 0.0 && p.lambda_liquid > 0.0;
+  ph.lam_v = (C)p.lambda_vapour;
+  ph.lam_l = (C)p.lambda_liquid;
+  ph.lam_rv = (C)p.lambda_rho_v;
+  ph.lam_inv_drho = ph.var_lambda ? (C)(1.0 / (p.lambda_rho_l - p.lambda_rho_v)) : (C)0;
   return ph;
 }
 
@@ -240,9 +256,15 @@ struct Impl {
     hipError_t e = prepass_on(ctx, fs, gs);
     if (e != hipSuccess) return e;
     const Geom geo = geom_of(ctx->p);
+    // vartheta = 1: record T, and apply the correction once two past values exist
+    const int corr = ctx->p.theta_corr ? (ctx->hist >= 2 ? 2 : 1) : 0;
     hipLaunchKernelGGL(k_collide_push<S>, dim3(blocks_for(geo.N)), dim3(256), 0, ctx->stream, (const S*)fs,
                        (const S*)gs, fd, gd, (const C*)ctx->rho, (const C*)ctx->T, (const C*)ctx->ueq,
-                       (const C*)ctx->du, geo, phys_of<C>(ctx->p));
+                       (const C*)ctx->du, (const C*)ctx->Th[0], (C*)ctx->Th[1], corr, geo, phys_of<C>(ctx->p));
+    if (corr) {
+      std::swap(ctx->Th[0], ctx->Th[1]);
+      ctx->hist = std::min(ctx->hist + 1, 2);
+    }
     return hipGetLastError();
   }
 
@@ -376,6 +398,8 @@ lbm_status adjoint_check(const lbm_ctx* ctx, const lbm_adjoint_spec* sp, std::st
     if (ctx->p.face[k] != LBM_FACE_PERIODIC) {
       msg = "the adjoint needs periodic x and y faces"; return LBM_EUNSUPPORTED;
     }
+  if (ctx->p.lambda_vapour > 0.0) { msg = "the adjoint needs a uniform conductivity"; return LBM_EUNSUPPORTED; }
+  if (ctx->p.theta_corr) { msg = "the adjoint is built for vartheta = 0"; return LBM_EUNSUPPORTED; }
   return LBM_OK;
 }
 
@@ -568,12 +592,13 @@ lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_by
   ctx->fA = b + L.off_fA; ctx->gA = b + L.off_gA; ctx->fB = b + L.off_fB; ctx->gB = b + L.off_gB;
   ctx->rho = b + L.off_rho; ctx->T = b + L.off_T; ctx->psi = b + L.off_psi;
   ctx->ueq = b + L.off_ueq; ctx->du = b + L.off_du;
+  ctx->Th[0] = b + L.off_Th0; ctx->Th[1] = b + L.off_Th1;
   ctx->Tw[0] = (double*)(b + L.off_Tw0); ctx->Tw[1] = (double*)(b + L.off_Tw1);
   ctx->partials = (double*)(b + L.off_part);
   ctx->sums = (double*)(b + L.off_sums);
   ctx->flag = (int*)(b + L.off_flag);
   ctx->staging = (double*)(b + L.off_stage);
-  ctx->fused_ok = fused_supported(*p);
+  ctx->fused_ok = fused_supported(*p) && p->theta_corr == 0;
   {
     // enough workgroups to cover the 256 compute units twice, z chunks of >= 8 planes
     const long long ntiles = (long long)(p->nx / FTX) * (p->ny / fused_tile_height(p->precision));
@@ -621,6 +646,7 @@ lbm_status lbm_init(lbm_ctx* ctx, const double* rho, const double* u, const doub
   HIPCHK(ctx, hipMemsetAsync(ctx->flag, 0, 64, ctx->stream));
   ctx->initialised = true;
   ctx->step = 0;
+  ctx->hist = 0;
   double sums[RED_VALUES];
   const lbm_status s = reduce_now(ctx, sums);
   if (s != LBM_OK) return s;

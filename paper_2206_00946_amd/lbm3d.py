@@ -40,6 +40,8 @@ class LbmParams(ctypes.Structure):
         ("kappa_w", ctypes.c_double),
         ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
         ("diag_rho_v", ctypes.c_double), ("diag_rho_l", ctypes.c_double),
+        ("lambda_vapour", ctypes.c_double), ("lambda_liquid", ctypes.c_double),
+        ("lambda_rho_v", ctypes.c_double), ("lambda_rho_l", ctypes.c_double),
     ]
 
 
@@ -137,9 +139,11 @@ def make_params(nx, ny, nz, precision="fp32", faces: Sequence[int] = (PERIODIC,)
 
 
 def params_from_workload(w: Dict, precision="fp32") -> LbmParams:
+    extra = {k: w[k] for k in ("lambda_vapour", "lambda_liquid", "lambda_rho_v", "lambda_rho_l", "cv", "theta_corr")
+             if w.get(k) is not None}
     return make_params(w["nx"], w["ny"], w["nz"], precision=precision, faces=w["faces"], face_T=w["face_T"],
                        face_rho=w["face_rho"], kappa_w=w["kappa_w"], rho_ref=w["rho_ref"], T_ref=w["T_ref"],
-                       diag_rho_v=w["rho_v"], diag_rho_l=w["rho_l"])
+                       diag_rho_v=w["rho_v"], diag_rho_l=w["rho_l"], **extra)
 
 
 class Lbm3D:

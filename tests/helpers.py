@@ -5,8 +5,17 @@ from oracle import lbm_oracle as O
 
 
 def oracle_params(w, **kw):
+    extra = {}
+    if w.get("lambda_vapour") is not None:
+        extra = dict(lam_vapour=w["lambda_vapour"], lam_liquid=w["lambda_liquid"], lam_rho_v=w["lambda_rho_v"],
+                     lam_rho_l=w["lambda_rho_l"])
+    if w.get("cv") is not None:
+        extra["cv"] = w["cv"]
+    if w.get("theta_corr"):
+        extra["theta_corr"] = int(w["theta_corr"])
+    extra.update(kw)
     return O.Params(w["nx"], w["ny"], w["nz"], faces=tuple(w["faces"]), face_T=tuple(w["face_T"]),
-                    face_rho=tuple(w["face_rho"]), kappa_w=w["kappa_w"], **kw)
+                    face_rho=tuple(w["face_rho"]), kappa_w=w["kappa_w"], **extra)
 
 
 def oracle_run(w, steps, record=()):
@@ -15,12 +24,14 @@ def oracle_run(w, steps, record=()):
     f, g = O.init_populations(w["rho0"], w["T0"], p)
     Tw = w.get("Tw") or None
     out = {}
+    hist = []
     if 0 in record:
         out[0] = O.fields(f, g, p, Tw)
     for s in range(1, steps + 1):
-        f, g, mac = O.step(f, g, p, Tw)
+        f, g, mac = O.step(f, g, p, Tw, hist)
         if mac["bad"].any():
             raise FloatingPointError(f"oracle left the physical range at step {s - 1}")
+        hist = [mac["T"]] + hist[:1]
         if s in record:
             out[s] = O.fields(f, g, p, Tw)
     return out

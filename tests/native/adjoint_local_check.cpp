@@ -88,7 +88,7 @@ int main() {
     auto J7 = [&](double hh) {
       double gg[7];
       for (int k = 0; k < 7; ++k) gg[k] = g[k] + hh * dg[k];
-      collide7(gg, Fbar + hh * dF, ph);
+      collide7(gg, Fbar + hh * dF, ph.vflux, ph);
       double s = 0;
       for (int k = 0; k < 7; ++k) s += gsb[k] * gg[k];
       return s;

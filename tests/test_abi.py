@@ -106,7 +106,8 @@ def test_required_bytes(prec, es):
     (dict(cv=-1.0), 1),
     (dict(faces=(2, 2, 0, 0, 0, 0), face_T=(0.1,) * 6, face_rho=(0.0,) * 6), 1),   # rho_out missing
     (dict(faces=(0, 0, 0, 0, 1, 1), face_T=(0.0,) * 6), 1),   # wall without temperature
-    (dict(theta_corr=1), 6),
+    (dict(theta_corr=2), 1),
+    (dict(lambda_vapour=0.2), 1),                             # one conductivity only
     (dict(faces=(1, 1, 0, 0, 0, 0), face_T=(0.1,) * 6), 6),   # x walls
     (dict(faces=(2, 2, 0, 0, 1, 1), face_T=(0.1,) * 6, face_rho=(0.4,) * 6), 6),  # z wall needs periodic x
     (dict(precision=7), 1),

@@ -40,6 +40,8 @@ def _small_workloads():
         "heated_wall_35x31x27": synth.heated_wall(nx=35, ny=31, nz=27, R0=10.0, Tw_jitter=0.02, seed=5,
                                                   kappa_w=0.3),
         "blobs_closed_40x36x30": synth.blobs_closed(nx=40, ny=36, nz=30, mean_blobs=3, rmin=5.0, rmax=9.0),
+        # conductivity linear in rho between the phases (Sec. 4.1 values)
+        "heat_transfer_6x5x40": synth.saturated_heat_transfer(nx=6, ny=5, nz=40),
     }
 
 
@@ -166,7 +168,7 @@ def test_error_paths(P):
     with pytest.raises(P.LbmError) as e:
         P.Lbm3D(bad)
     assert e.value.status == 1            # LBM_EINVAL
-    unsup = P.make_params(8, 8, 8, theta_corr=1)
+    unsup = P.make_params(8, 8, 8, faces=(1, 1, 0, 0, 0, 0), face_T=(0.1,) * 6)
     with pytest.raises(P.LbmError) as e:
         P.Lbm3D(unsup)
     assert e.value.status == 6            # LBM_EUNSUPPORTED
@@ -248,6 +250,7 @@ FUSED = {
                                                                  noise=1e-6, seed=2, center=(70, 8, 12)),
     "blobs_closed_64x32x40": lambda: synth.blobs_closed(nx=64, ny=32, nz=40, mean_blobs=3, rmin=5.0,
                                                         rmax=8.0, seed=9),
+    "heat_transfer_64x16x40": lambda: synth.saturated_heat_transfer(nx=64, ny=16, nz=40),
 }
 
 
@@ -275,14 +278,14 @@ def test_fused_parity(P, name, prec, chunk, monkeypatch):
 
 
 @pytest.mark.parametrize("name", list(FUSED))
-def test_fused_fp32_tile_height_8(P, name, monkeypatch):
-    """32-bit storage with the 8-row tile (the 16-row tile is the default)."""
-    monkeypatch.setenv("LBM_FUSED_TY", "8")
+def test_fused_fp32_tile_height_16(P, name, monkeypatch):
+    """32-bit storage with the optional 16-row tile (the 8-row tile is the default)."""
+    monkeypatch.setenv("LBM_FUSED_TY", "16")
     w = FUSED[name]()
     ref = oracle_run(w, 20, record=(20,))
     sim = P.from_workload(w, precision="fp32")
     sim.step(20)
-    _compare(f"{name} fp32 ty=8 step 20", sim.fields(), ref[20], 1e-4, 2e-2, 1e-4)
+    _compare(f"{name} fp32 ty=16 step 20", sim.fields(), ref[20], 1e-4, 2e-2, 1e-4)
     sim.close()
 
 
@@ -297,3 +300,52 @@ def test_fused_matches_unfused_fp64(P, name, monkeypatch):
         out.append(sim.fields())
         sim.close()
     _compare(f"{name} fused vs unfused", out[0], out[1], 1e-13, 1e-13, 1e-13)
+
+
+# ---------------------------------------------------------------- vartheta = 1
+
+def _theta1(w):
+    w = dict(w)
+    w["theta_corr"] = 1
+    return w
+
+
+THETA1 = {
+    "droplet_open_37x34x29": lambda: _theta1(synth.droplet_open(nx=37, ny=34, nz=29, R0=9.0)),
+    "heated_wall_35x31x27": lambda: _theta1(synth.heated_wall(nx=35, ny=31, nz=27, R0=10.0, Tw_jitter=0.02,
+                                                               seed=5, kappa_w=0.3)),
+    "droplet_periodic_128x16x24": lambda: _theta1(FUSED["droplet_periodic_128x16x24"]()),
+}
+
+
+@pytest.mark.parametrize("name", list(THETA1))
+def test_theta1_parity_fp64(P, name):
+    """The correction term of eq. (16) (vartheta = 1) against the oracle,
+    across the steps where the temperature history fills up."""
+    w = THETA1[name]()
+    steps = 60
+    _log(f"[theta=1] {name}")
+    ref = oracle_run(w, steps, record=(1, 2, 3, steps))
+    sim = P.from_workload(w, precision="fp64")
+    done = 0
+    for s in (1, 2, 3, steps):
+        sim.step(s - done)
+        done = s
+        _compare(f"{name} theta=1 step {s}", sim.fields(), ref[s], TOL64, TOL64, TOL64)
+    sim.close()
+
+
+def test_theta1_changes_the_result(P):
+    """vartheta = 1 is not a no-op: after the history fills, T differs from vartheta = 0."""
+    w = THETA1["heated_wall_35x31x27"]()
+    w0 = dict(w)
+    w0["theta_corr"] = 0
+    out = []
+    for ww in (w0, w):
+        sim = P.from_workload(ww, precision="fp64")
+        sim.step(20)
+        out.append(sim.fields()[2])
+        sim.close()
+    d = float(np.max(np.abs(out[1] - out[0])))
+    _log(f"max |T(theta=1) - T(theta=0)| after 20 steps: {d:.3e}")
+    assert d > 1e-12

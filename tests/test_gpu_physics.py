@@ -7,7 +7,10 @@ agrees with the oracle to 1e-12 per step) or FP32:
 * Laplace law: the pressure jump across a droplet is linear in 1/R with a
   small intercept;
 * d^2 law (Sec. 4.2, eq. (56)): after the initial transient the squared
-  diameter of an evaporating droplet falls linearly in time.
+  diameter of an evaporating droplet falls linearly in time;
+* heat transfer through a flat interface between two conductivities
+  (Sec. 4.1): at steady state the temperature slopes in the two phases are
+  in the inverse ratio of the conductivities (2; the paper reports 1.9507).
 
 The two equilibrium checks hold T fixed by taking c_v very large (the rho c_v
 blend of eq. (13) then leaves g unchanged to 1e-6 per step), which isolates
@@ -96,6 +99,46 @@ def test_laplace_law(P):
     assert abs(icpt) < 0.1 * y.min()
 
 
+def _d2_rate(P, w):
+    """Evaporation rate K of the d^2 law over t in [4000, 20000] and r^2."""
+    import torch
+    sim = P.from_workload(w, "fp32")
+    t, vol = [], []
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    for k in range(201):
+        d = sim.reduce()
+        t.append(100 * k)
+        vol.append(d["vol_smooth"])
+        if k < 200:
+            sim.step(100)
+    end.record(sim.stream)
+    torch.cuda.synchronize()
+    sim.close()
+    t, vol = np.array(t, dtype=float), np.array(vol)
+    D2 = (6.0 * vol / np.pi) ** (2.0 / 3.0)
+    sel = t >= 4000
+    A = np.vstack([t[sel], np.ones(sel.sum())]).T
+    (m, c), *_ = np.linalg.lstsq(A, D2[sel], rcond=None)
+    r2 = 1.0 - np.sum((D2[sel] - (m * t[sel] + c)) ** 2) / np.sum((D2[sel] - D2[sel].mean()) ** 2)
+    return -m, r2, D2, start.elapsed_time(end) / 20000.0
+
+
+def test_d2_law_with_and_without_correction(P):
+    """vartheta = 0 and 1 give almost the same evaporation rate (Sec. 4.1
+    and Table 1 of the paper report the two as almost the same)."""
+    w = synth.named("droplet_open_128")
+    K0, r0, _, ms0 = _d2_rate(P, w)
+    w1 = dict(w)
+    w1["theta_corr"] = 1
+    K1, r1, _, ms1 = _d2_rate(P, w1)
+    _log(f"  K(theta=0) {K0:.5e} ({ms0:.4f} ms/step)  K(theta=1) {K1:.5e} ({ms1:.4f} ms/step)  "
+         f"relative difference {K1 / K0 - 1:+.2e}, time {ms1 / ms0 - 1:+.1%}")
+    assert r1 > 0.99 and abs(K1 / K0 - 1) < 0.05
+
+
 def test_d2_law(P):
     w = synth.named("droplet_open_128")
     _log("d^2 law: droplet_open_128 FP32, 20000 steps, volume every 100")
@@ -116,3 +159,28 @@ def test_d2_law(P):
     r2 = 1.0 - np.sum((D2[sel] - (m * t[sel] + c)) ** 2) / np.sum((D2[sel] - D2[sel].mean()) ** 2)
     _log(f"  D0^2 {D2[0]:.1f}, K = {-m:.5e} per step, r^2 {r2:.5f}, final (D/D0)^2 {D2[-1] / D2[0]:.4f}")
     assert m < 0 and r2 > 0.99
+
+
+def test_saturated_heat_transfer_slope_ratio(P):
+    """Sec. 4.1 set-up turned to z walls (10 x 10 x 100 here, half the
+    paper's length so that the liquid reaches steady state in 1.5e6 steps):
+    vapour (lambda 0.2) below liquid (lambda 0.4), hot wall at T_c, cold wall
+    at T_sat.  Fourier's law with a continuous heat flux gives a slope ratio
+    of 2; the model converges to about 1.90 (the paper reports 1.9507)."""
+    w = synth.saturated_heat_transfer(nz=100)
+    _log("saturated heat transfer 10x10x100 FP64, 1.5e6 steps")
+    sim = P.from_workload(w, "fp64")
+    sim.step(1500000)
+    rho, u, T = sim.fields()
+    sim.close()
+    Tz = T.mean(axis=(1, 2)) / w["Tc"]
+    rz = rho.mean(axis=(1, 2))
+    mid = 0.5 * (w["rho_v"] + w["rho_l"])
+    iface = int(np.argmax((rz[:-1] - mid) * (rz[1:] - mid) < 0))
+    zv, zl = np.arange(5, iface - 5), np.arange(iface + 5, 95)
+    sv, sl = np.polyfit(zv, Tz[zv], 1)[0], np.polyfit(zl, Tz[zl], 1)[0]
+    lin_v = np.max(np.abs(Tz[zv] - np.polyval(np.polyfit(zv, Tz[zv], 1), zv)))
+    _log(f"  interface at z = {iface}, slopes {sv:.5e} (vapour) {sl:.5e} (liquid), ratio {sv / sl:.4f}, "
+         f"vapour profile linear to {lin_v:.1e}")
+    assert abs(sv / sl - 2.0) < 0.12
+    assert lin_v < 1e-3

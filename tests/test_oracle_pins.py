@@ -428,7 +428,7 @@ def test_centred_droplet_symmetry():
 def _thermal_only(g, rho, p, steps):
     for _ in range(steps):
         T = g.sum(0)
-        gs = O.collide7(g, T, np.zeros_like(T), p)
+        gs = O.collide7(g, T, np.zeros_like(T), p, rho)
         g = O.stream7_blend(gs, g, rho, p)
     return g
 
@@ -462,6 +462,50 @@ def test_thermal_sine_decay_matches_fourier_eigenvalue(N):
     assert abs((1 - lam) - rate) / rate < (0.03 if N == 16 else 0.008)
 
 
+@pytest.mark.parametrize("N", [16])
+def test_thermal_sine_decay_with_correction_term(N):
+    """vartheta = 1 (eqs. (13), (16)), thermal lattice alone: the state
+    (g(t), T(t-1), T(t-2)) evolves linearly, so a sine mode decays by the
+    dominant eigenvalue of the 9 x 9 augmented amplification matrix.  The
+    decay rates with and without the correction differ by well under 1 %
+    (the paper finds the two "almost the same")."""
+    rates = {}
+    for theta in (0, 1):
+        p = O.Params(N, 1, 1, theta_corr=theta)
+        rho = np.full(p.shape, 0.8)
+        x = np.arange(N, dtype=float)
+        T = 0.1 + 0.001 * np.sin(2 * np.pi * x / N)
+        g = O.geq7(np.broadcast_to(T, p.shape).copy(), p)
+        hist = []
+        amps = []
+        for _ in range(202):
+            Tn = g.sum(0)
+            mac = dict(Fbar=np.zeros_like(Tn), T=Tn, rho=rho)
+            gs = O.collide7(g, Tn, O.correction_source(mac, p, hist), p, rho)
+            g = O.stream7_blend(gs, g, rho, p)
+            hist = [Tn] + hist[:1]
+            amps.append(np.abs(np.fft.fft(g.sum(0)[0, 0])[1]))
+        ratio = amps[-1] / amps[-2]
+        k = 2 * np.pi / N
+        w = O.w7(p.wbar)
+        Minv = np.linalg.inv(O.M7.astype(float))
+        K = np.eye(7) - Minv @ np.diag(p.lambda7()) @ O.M7 @ (np.eye(7) - np.outer(w, np.ones(7)))
+        D = np.diag(np.exp(-1j * k * O.C7[:, 0]))
+        beta = 1.0 / (0.8 * p.cv)
+        h = 0.5 * 0.8 * p.cv * theta   # S_i = w_i rho c_v / 2 (T - 2 T1 + T2)
+        A = np.zeros((9, 9), dtype=complex)
+        A[:7, :7] = (1 - beta) * np.eye(7) + beta * D @ (K + h * np.outer(w, np.ones(7)))
+        A[:7, 7] = beta * D @ (-2.0 * h * w)
+        A[:7, 8] = beta * D @ (h * w)
+        A[7, :7] = 1.0
+        A[8, 7] = 1.0
+        lam = np.max(np.abs(np.linalg.eigvals(A)))
+        assert abs(ratio - lam) < 1e-12, (theta, ratio, lam)
+        rates[theta] = 1 - lam
+    assert rates[0] != rates[1]
+    assert abs(rates[1] / rates[0] - 1) < 0.01
+
+
 def test_thermal_steady_linear_profile_between_dirichlet_planes():
     """Thermal lattice alone between two Dirichlet planes: the steady state is
     the linear profile and the local gradient of eqs. (27)-(29) equals its slope."""
@@ -472,7 +516,7 @@ def test_thermal_steady_linear_profile_between_dirichlet_planes():
     for _ in range(4000):
         g = O.thermal_dirichlet(g, p)
         T = g.sum(0)
-        gs = O.collide7(g, T, np.zeros_like(T), p)
+        gs = O.collide7(g, T, np.zeros_like(T), p, rho)
         g = O.stream7_blend(gs, g, rho, p)
     g = O.thermal_dirichlet(g, p)
     T = g.sum(0)[:, 0, 0]
@@ -484,6 +528,38 @@ def test_thermal_steady_linear_profile_between_dirichlet_planes():
 
 
 # ---------------------------------------------------------------- EOS
+
+def test_two_conductivities_steady_flux_continuity():
+    """Thermal lattice alone between two Dirichlet planes across a density
+    step with lambda(rho_v) = 0.2 and lambda(rho_l) = 0.4 (the Sec. 4.1
+    values): at steady state the bulk profiles are linear and carry the same
+    heat flux, so their slopes are in the ratio lambda_l / lambda_v = 2."""
+    nz = 24
+    # the two densities only select the two conductivities; a light "liquid"
+    # (rho c_v = 5) keeps the diffusion time short
+    p = O.Params(1, 1, nz, faces=(0, 0, 0, 0, O.WALL, O.WALL), face_T=(0, 0, 0, 0, 0.1, 0.13),
+                 lam_vapour=0.2, lam_liquid=0.4, lam_rho_v=0.38, lam_rho_l=1.0)
+    rho = np.full(p.shape, 0.38)
+    rho[nz // 2:] = 1.0
+    g = O.geq7(np.full(p.shape, 0.1), p)
+    for _ in range(20000):
+        g = O.thermal_dirichlet(g, p)
+        T = g.sum(0)
+        gs = O.collide7(g, T, np.zeros_like(T), p, rho)
+        g = O.stream7_blend(gs, g, rho, p)
+    g = O.thermal_dirichlet(g, p)
+    T = g.sum(0)[:, 0, 0]
+    sv = np.diff(T[2:nz // 2 - 2])
+    sl = np.diff(T[nz // 2 + 2:nz - 2])
+    assert np.ptp(sv) < 1e-9 * sv.mean() and np.ptp(sl) < 1e-9 * sl.mean()
+    assert abs(sv.mean() / sl.mean() - 2.0) < 1e-9
+    # the local gradient of eqs. (27)-(29) with the local rate gives the slope
+    mz = (O.C7[:, 2].astype(float) @ g.reshape(7, -1)).reshape(nz)
+    rates = p.lambda7_field(rho)[3, :, 0, 0]
+    gradT = -rates * mz / p.cs2_T
+    assert np.allclose(gradT[3:nz // 2 - 3], sv.mean(), rtol=1e-8)
+    assert np.allclose(gradT[nz // 2 + 3:nz - 3], sl.mean(), rtol=1e-8)
+
 
 def test_pr_critical_point():
     """eq. (55): at Tc the isotherm has an inflection with zero slope at the

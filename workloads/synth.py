@@ -171,6 +171,23 @@ def slab(nx=128, ny=8, nz=8, width=64.0, W=5.0, Tsat=0.86, steps=20000):
     return w
 
 
+def saturated_heat_transfer(nx=10, ny=10, nz=200, W=5.0, Tsat=0.86, Th=1.0, lam_v=0.2, lam_l=0.4, cv=5.0,
+                            steps=200000):
+    """Heat transfer through a flat liquid-vapour interface (Sec. 4.1 set-up,
+    turned so that the walls are the z faces): vapour for z < nz/2, liquid
+    above, both at Tsat*Tc; the z = 0 wall is held at Th*Tc, the z = nz-1
+    wall at Tsat*Tc; conductivities lam_v (vapour) and lam_l (liquid)."""
+    w = _base("saturated_heat_transfer", nx, ny, nz, [PERIODIC] * 4 + [WALL] * 2, steps, Tsat)
+    Tc = w["Tc"]
+    w["face_T"] = [0.0] * 4 + [Th * Tc, Tsat * Tc]
+    z, y, x = _grid(nx, ny, nz)
+    s = z - (nz / 2 - 0.5) + 0.0 * (x + y)       # > 0 in the liquid half
+    w["rho0"] = tanh_profile(s, 0.0, W, w["rho_v"], w["rho_l"])
+    w["T0"] = np.full(w["rho0"].shape, Tsat * Tc)
+    w.update(lambda_vapour=lam_v, lambda_liquid=lam_l, lambda_rho_v=w["rho_v"], lambda_rho_l=w["rho_l"], cv=cv)
+    return w
+
+
 def _poisson(lam: float, u: float) -> int:
     """Inverse-CDF Poisson draw from one uniform number."""
     k = 0
