@@ -3,9 +3,10 @@
 // 2206.00946, Sec. 2 and 3.1).
 //
 // Domain: periodic in x and y; z periodic or bounded by two no-slip walls
-// with a 90 degree contact angle (kappa_w = 0, so the ghost psi of eq. (37)
-// mirrors the first interior layer).  nx must be a multiple of 64 and ny a
-// multiple of the tile height.  Other set-ups use the unfused kernels.
+// (ghost psi of eq. (37): the first interior layer plus kappa_w times the
+// tangential difference magnitude on the wall layer).  nx must be a multiple
+// of 64 and ny a multiple of the tile height.  Other set-ups use the
+// unfused kernels.
 //
 // A workgroup owns a 64 x TY column tile (one wavefront per row, one thread
 // per column) and marches through z.  For every plane p it loads the
@@ -394,13 +395,23 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       const bool wall_plane = !ST && a.zwall && (zq == 0 || zq == nz - 1);
       const int sq = (k + 1) & 1;  // ueq slot of plane q
       const int rq = (k + 3) & 3;  // rho slot of plane q
+      // eq. (37): the ghost layer adds kappa_w |grad_t psi| of the wall layer
+      // (periodic tangential differences, all within the 2-cell halo for the
+      // tile's own cells)
+      const int gdir = !wall_plane || ph.kappa_w == C(0) ? 0 : (zq == 0 ? -1 : 1);
       auto force_at = [&](int e, C& Fx, C& Fy, C& Fz) {
         C ax = C(0), ay = C(0), az = C(0);
 #pragma unroll
         for (int i = 1; i < 19; ++i) {
           const C wgt = i < 7 ? C(1) / C(6) : C(1) / C(12);
           const int slot = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-          const C pn = s_psi[slot][e + CX[i] + CY[i] * EX];
+          const int en = e + CX[i] + CY[i] * EX;
+          C pn = s_psi[slot][en];
+          if (gdir != 0 && CZ[i] == gdir) {
+            const C tx = s_psi[s0][en + 1] - s_psi[s0][en - 1];
+            const C ty = s_psi[s0][en + EX] - s_psi[s0][en - EX];
+            pn += ph.kappa_w * fsqrt(tx * tx + ty * ty);
+          }
           if (CX[i]) ax += wgt * C(CX[i]) * pn;
           if (CY[i]) ay += wgt * C(CY[i]) * pn;
           if (CZ[i]) az += wgt * C(CZ[i]) * pn;
@@ -451,15 +462,17 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         }
       }
       if (has_ring) {
-        C Fx, Fy, Fz;
-        force_at(re, Fx, Fy, Fz);
-        // same operation order as the tile's own u, so that u does not
-        // depend on which thread evaluates it
-        const C ir = rcp(s_rho[rq][re]);
-        C vx = s_ueq[sq][0][re] + C(0.5) * (Fx * ir);
-        C vy = s_ueq[sq][1][re] + C(0.5) * (Fy * ir);
-        C vz = s_ueq[sq][2][re] + C(0.5) * (Fz * ir);
-        if (wall_plane) vx = vy = vz = C(0);
+        // u vanishes on wall nodes; elsewhere the same operation order as the
+        // tile's own u, so that u does not depend on which thread evaluates it
+        C vx = C(0), vy = C(0), vz = C(0);
+        if (!wall_plane) {
+          C Fx, Fy, Fz;
+          force_at(re, Fx, Fy, Fz);
+          const C ir = rcp(s_rho[rq][re]);
+          vx = s_ueq[sq][0][re] + C(0.5) * (Fx * ir);
+          vy = s_ueq[sq][1][re] + C(0.5) * (Fy * ir);
+          vz = s_ueq[sq][2][re] + C(0.5) * (Fz * ir);
+        }
         s_u[0][re] = vx;
         s_u[1][re] = vy;
         s_u[2][re] = vz;
@@ -593,7 +606,6 @@ inline bool fused_supported(const lbm_params& p) {
   const bool zper = p.face[4] == LBM_FACE_PERIODIC && p.face[5] == LBM_FACE_PERIODIC;
   const bool zwall = p.face[4] == LBM_FACE_WALL && p.face[5] == LBM_FACE_WALL;
   if (!zper && !zwall) return false;
-  if (zwall && p.kappa_w != 0.0) return false;
   const int ty = fused_tile_height(p.precision);
   if (p.nx % FTX != 0 || p.ny % ty != 0) return false;
   if (p.nz < 4) return false;

@@ -245,12 +245,23 @@ def test_full_size_sampled(P, name, prec):
 
 # ---------------------------------------------------------------- fused single-pass kernel
 
+def _closed(w):
+    """A heated-wall workload with its outlet replaced by a second wall."""
+    w = dict(w)
+    w["faces"] = list(w["faces"][:5]) + [1]
+    w["face_T"] = list(w["face_T"][:5]) + [w["face_T"][4]]
+    return w
+
+
 FUSED = {
     "droplet_periodic_128x16x24": lambda: synth.droplet_periodic(nx=128, ny=16, nz=24, R0=6.0, W=5.0,
                                                                  noise=1e-6, seed=2, center=(70, 8, 12)),
     "blobs_closed_64x32x40": lambda: synth.blobs_closed(nx=64, ny=32, nz=40, mean_blobs=3, rmin=5.0,
                                                         rmax=8.0, seed=9),
     "heat_transfer_64x16x40": lambda: synth.saturated_heat_transfer(nx=64, ny=16, nz=40),
+    # wetting ghost layer with kappa_w != 0 on both walls
+    "wetting_64x16x24": lambda: _closed(synth.heated_wall(nx=64, ny=16, nz=24, R0=6.0, Tw_jitter=0.02, seed=5,
+                                                          kappa_w=0.3)),
 }
 
 
