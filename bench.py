@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--variant-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--accuracy-steps", type=int, default=50,
+                    help="steps of the FP64-referenced accuracy check of the storage precisions (0: skip)")
     ap.add_argument("--adjoint-workload", default="heated_wall_adjoint_96",
                     help="workload of the adjoint timing ('' to skip)")
     ap.add_argument("--adjoint-precisions", default="fp64,fp32")
@@ -57,15 +59,30 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+# sources that determine the single-pass step kernel (and the flags it is built with)
+FUSED_SOURCES = ["paper_2206_00946_amd/csrc/kernels_fused.h", "paper_2206_00946_amd/csrc/kernels_ref.h",
+                 "paper_2206_00946_amd/csrc/lattice.h", "paper_2206_00946_amd/csrc/storage.h",
+                 "include/lbm3d.h", "paper_2206_00946_amd/build.py"]
+
+
+def fused_kernel_hash():
+    h = hashlib.sha256()
+    for rel in FUSED_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(rel.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(workload, prec, launches_cells):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources (else None)."""
+    it was taken on the current sources of the step kernel (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_hash") != source_hash():
+    if t.get("kernel_hash") != fused_kernel_hash():
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -93,6 +110,31 @@ def time_precision(P, torch, w, prec, steps, warmup):
     achieved = ALG_BYTES[prec] * cells / (ms * 1e-3) / 1e9
     return dict(ms_per_step=ms, mlups=mlups, wall_s=wall, achieved_gbs=achieved,
                 frac=achieved / PEAK_HBM_GBS, mass=diag["mass"])
+
+
+def accuracy_vs_fp64(P, torch, w, precs, steps):
+    """Max relative error of rho and T (and normwise u) of each storage
+    precision against FP64 storage after `steps` steps of the same workload
+    (FP64 on the GPU equals the FP64 oracle to 1e-12, see the parity tests)."""
+    def run(prec):
+        sim = P.from_workload(w, precision=prec)
+        sim.step(steps)
+        out = sim.fields_device()
+        sim.close()
+        return out
+    ref = run("fp64")
+    res = {}
+    for prec in precs:
+        got = run(prec)
+        er = float(((got[0] - ref[0]).abs() / ref[0].abs()).max())
+        eT = float(((got[2] - ref[2]).abs() / ref[2].abs()).max())
+        eu = float((got[1] - ref[1]).abs().max() / ref[1].abs().max())
+        res[prec] = dict(rho_max_rel=er, T_max_rel=eT, u_normwise=eu)
+        del got
+        torch.cuda.empty_cache()
+    del ref
+    torch.cuda.empty_cache()
+    return res
 
 
 def time_adjoint(P, torch, w, prec):
@@ -187,6 +229,11 @@ def main():
         r = time_precision(P, torch, w, prec, vsteps, max(2, args.warmup // 2))
         variants[prec] = dict(mlups=round(r["mlups"], 1), ms_per_step=round(r["ms_per_step"], 4),
                               alg_bytes_per_cell=ALG_BYTES[prec], roofline_frac=round(r["frac"], 4))
+    accuracy = None
+    if args.accuracy_steps:
+        print(f"[bench] accuracy vs fp64 storage, {args.accuracy_steps} steps", file=sys.stderr, flush=True)
+        accuracy = {"steps": args.accuracy_steps, "reference": "fp64 storage (= oracle to 1e-12)"}
+        accuracy.update(accuracy_vs_fp64(P, torch, w, [p for p in ["fp32", "fp16", "bf16"]], args.accuracy_steps))
     adjoint = None
     if args.adjoint_workload:
         wa = synth.named(args.adjoint_workload)
@@ -215,8 +262,10 @@ def main():
                      "unit": "GB/s", "frac": round(head["frac"], 4), "traffic": traffic,
                      "alg_bytes_per_cell": ALG_BYTES[args.precision]},
         "variants": variants,
+        "accuracy": accuracy,
         "adjoint": adjoint,
         "source_hash": source_hash(),
+        "kernel_hash": fused_kernel_hash(),
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -264,12 +264,14 @@ __global__ void __launch_bounds__(256)
 // Reverse of the wetting ghost layer of eq. (37) on each wall face, one
 // thread per (x, y): psi_ghost = psi(x, y, z_in) + kappa_w |grad_t psi(x, y, z_w)|.
 // gadj = adjoint of psi_ghost (from the force of the wall-plane readers);
-// ax, ay route it to the tangential differences; kap = its kappa_w part.
+// ax, ay route it to the tangential differences; kap accumulates its kappa_w
+// part over the reverse sweep (FP64, one entry per wall node, summed once at
+// the end).
 // Planes are indexed face * nx*ny + x + nx*y, face 0 = -z, 1 = +z.
 template <typename C>
 __global__ void __launch_bounds__(256) k_adj_ghost(const C* __restrict__ Fb, const C* __restrict__ psi,
                                                    C* __restrict__ gadj, C* __restrict__ ax, C* __restrict__ ay,
-                                                   C* __restrict__ kap, Geom g, Phys<C> ph) {
+                                                   double* __restrict__ kap, Geom g, Phys<C> ph) {
   const long long P = (long long)g.nx * g.ny;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P) return;
@@ -277,10 +279,7 @@ __global__ void __launch_bounds__(256) k_adj_ghost(const C* __restrict__ Fb, con
   const long long N = g.N;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    if (g.face[4 + s] != FACE_WALL) {
-      kap[s * P + t] = C(0);
-      continue;
-    }
+    if (g.face[4 + s] != FACE_WALL) continue;
     const int zw = s ? g.nz - 1 : 0;
     const int out = s ? 1 : -1;
     C G = C(0);
@@ -295,7 +294,7 @@ __global__ void __launch_bounds__(256) k_adj_ghost(const C* __restrict__ Fb, con
     const C dy = psi[cell_index(g, x, wrapp(y + 1, g.ny), zw)] - psi[cell_index(g, x, wrapp(y - 1, g.ny), zw)];
     const C sq = sqrt(dx * dx + dy * dy);
     gadj[s * P + t] = G;
-    kap[s * P + t] = G * sq;
+    kap[s * P + t] += (double)(G * sq);
     // d sqrt(s) at s = 0 is taken as 0
     ax[s * P + t] = sq > C(0) ? G * ph.kappa_w * dx / sq : C(0);
     ay[s * P + t] = sq > C(0) ? G * ph.kappa_w * dy / sq : C(0);

@@ -380,7 +380,7 @@ AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp) {
   a.off_gadj = o; o = align_up(o + 2 * P * cs);
   a.off_ax = o; o = align_up(o + 2 * P * cs);
   a.off_ay = o; o = align_up(o + 2 * P * cs);
-  a.off_kap = o; o = align_up(o + 2 * P * cs);
+  a.off_kap = o; o = align_up(o + 2 * P * 8);
   a.off_grad = o; o = align_up(o + P * 8);
   a.off_acc = o; o = align_up(o + 64);
   a.total = o;
@@ -449,7 +449,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   C* gadj = (C*)(b + a.off_gadj);
   C* ax = (C*)(b + a.off_ax);
   C* ay = (C*)(b + a.off_ay);
-  C* kap = (C*)(b + a.off_kap);
+  double* kap = (double*)(b + a.off_kap);
   double* grad = (double*)(b + a.off_grad);
   double* acc = (double*)(b + a.off_acc);
   const hipStream_t st = ctx->stream;
@@ -484,6 +484,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   hipLaunchKernelGGL(k_adj_seed<C>, dim3(nb), dim3(256), 0, st, lf[0], lg[0], geo);
   HIPCHK(ctx, hipMemsetAsync(grad, 0, P * 8, st));
   HIPCHK(ctx, hipMemsetAsync(acc, 0, 64, st));
+  HIPCHK(ctx, hipMemsetAsync(kap, 0, 2 * P * 8, st));
   int cur = 0;
   for (int k = a.nseg - 1; k >= 0; --k) {
     const int len = std::min(a.L, a.nsteps - k * a.L);
@@ -506,11 +507,11 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
                          (const C*)a_T, (const C*)a_ueq, (const C*)a_du, (const C*)ctx->psi, (const C*)ctx->rho,
                          (const C*)ctx->T, (const C*)gadj, (const C*)ax, (const C*)ay, geo, ph);
       hipLaunchKernelGGL(k_adj_dirichlet<C>, dim3(npb), dim3(256), 0, st, lg[nx], grad, (int)sp.wall_face, geo, ph);
-      if (walls) hipLaunchKernelGGL(k_accumulate<C>, dim3(1), dim3(RED_THREADS), 0, st, (const C*)kap, 2 * P, acc);
       HIPCHK(ctx, hipGetLastError());
       cur = nx;
     }
   }
+  if (walls) hipLaunchKernelGGL(k_accumulate<double>, dim3(1), dim3(RED_THREADS), 0, st, (const double*)kap, 2 * P, acc);
   double kappa_grad = 0.0;
   HIPCHK(ctx, hipMemcpyAsync(&kappa_grad, acc, sizeof(double), hipMemcpyDeviceToHost, st));
   if (dJ_dTw)
