@@ -66,6 +66,7 @@ __global__ void __launch_bounds__(256)
                   const S* __restrict__ gA, const S* __restrict__ gnext,
                   const typename Storage<S>::C* __restrict__ rho_f, const typename Storage<S>::C* __restrict__ T_f,
                   const typename Storage<S>::C* __restrict__ ueq, const typename Storage<S>::C* __restrict__ du,
+                  const typename Storage<S>::C* __restrict__ ureal,
                   typename Storage<S>::C* __restrict__ lfo, typename Storage<S>::C* __restrict__ lgo,
                   typename Storage<S>::C* __restrict__ a_rho, typename Storage<S>::C* __restrict__ a_T,
                   typename Storage<S>::C* __restrict__ a_ueq, typename Storage<S>::C* __restrict__ a_du,
@@ -119,12 +120,23 @@ __global__ void __launch_bounds__(256)
   C gx, gy, gz;
   local_gradT(gp, ph.vflux, ph, gx, gy, gz);
   const C rux = ux + C(0.5) * dux, ruy = uy + C(0.5) * duy, ruz = uz + C(0.5) * duz;
+  // div u from the stored real velocity (the forward's u_at values): 0
+  // beyond walls, copy beyond outlets, wrap if periodic
   C div = C(0);
 #pragma unroll
   for (int i = 1; i < 19; ++i) {
-    C vx, vy, vz;
-    u_at(ueq, du, g, x + CX[i], y + CY[i], z + CZ[i], vx, vy, vz);
-    div += C(3) * w19<C>(i) * (C(CX[i]) * vx + C(CY[i]) * vy + C(CZ[i]) * vz);
+    const int xn = wrapp(x + CX[i], g.nx), yn = wrapp(y + CY[i], g.ny);
+    int zn = z + CZ[i];
+    C v = C(0);
+    if (z_inside(g, zn) || g.face[zn < 0 ? 4 : 5] == FACE_PRESSURE) {
+      if (zn < 0) zn = 0;
+      if (zn >= g.nz) zn = g.nz - 1;
+      const long long cn = cell_index(g, xn, yn, zn);
+      if (CX[i]) v += C(CX[i]) * ureal[cn];
+      if (CY[i]) v += C(CY[i]) * ureal[cn + N];
+      if (CZ[i]) v += C(CZ[i]) * ureal[cn + 2 * N];
+    }
+    div += C(3) * w19<C>(i) * v;
   }
   C dp_dr, dpdT, dpdT_dr, dpdT_dT;
   pr_partials(rho, T, ph, dp_dr, dpdT, dpdT_dr, dpdT_dT);

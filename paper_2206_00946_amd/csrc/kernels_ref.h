@@ -261,7 +261,8 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_force(S* __restrict__ fpop, const typename Storage<S>::C* __restrict__ rho_f,
                                                const typename Storage<S>::C* __restrict__ psi,
                                                typename Storage<S>::C* __restrict__ ueq,
-                                               typename Storage<S>::C* __restrict__ du, Geom g,
+                                               typename Storage<S>::C* __restrict__ du,
+                                               typename Storage<S>::C* __restrict__ ureal, Geom g,
                                                Faces<typename Storage<S>::C> fc,
                                                Phys<typename Storage<S>::C> ph) {
   using C = typename Storage<S>::C;
@@ -337,6 +338,11 @@ __global__ void __launch_bounds__(256) k_force(S* __restrict__ fpop, const typen
   du[c] = dux;
   du[c + g.N] = duy;
   du[c + 2 * g.N] = duz;
+  if (ureal) {  // the real velocity of eq. (5), in the operation order of u_at
+    ureal[c] = ux + C(0.5) * dux;
+    ureal[c + g.N] = uy + C(0.5) * duy;
+    ureal[c + 2 * g.N] = uz + C(0.5) * duz;
+  }
 }
 
 template <typename S>

@@ -232,7 +232,7 @@ struct Impl {
 
   // S0-S5 on the state (f, g): complete its boundary nodes in place and fill
   // rho, T, psi, u_eq, du.
-  static hipError_t prepass_on(lbm_ctx* ctx, S* f, S* g) {
+  static hipError_t prepass_on(lbm_ctx* ctx, S* f, S* g, C* ureal = nullptr) {
     const lbm_params& p = ctx->p;
     const Geom geo = geom_of(p);
     const Phys<C> ph = phys_of<C>(p);
@@ -243,7 +243,7 @@ struct Impl {
     hipLaunchKernelGGL(k_macro<S>, dim3(nb), dim3(256), 0, ctx->stream, f, g, (C*)ctx->rho, (C*)ctx->T,
                        (C*)ctx->psi, ctx->flag, geo, fc, ph);
     hipLaunchKernelGGL(k_force<S>, dim3(nb), dim3(256), 0, ctx->stream, f, (const C*)ctx->rho,
-                       (const C*)ctx->psi, (C*)ctx->ueq, (C*)ctx->du, geo, fc, ph);
+                       (const C*)ctx->psi, (C*)ctx->ueq, (C*)ctx->du, ureal, geo, fc, ph);
     return hipGetLastError();
   }
 
@@ -348,7 +348,8 @@ struct AdjPlan {
   int nsteps = 0, nseg = 0, L = 0;
   size_t fbytes = 0, gbytes = 0;
   size_t off_ck = 0, off_seg = 0, off_lf[2] = {0, 0}, off_lg[2] = {0, 0}, off_rho = 0, off_T = 0, off_div = 0,
-         off_ueq = 0, off_du = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0, off_acc = 0;
+         off_ueq = 0, off_du = 0, off_ureal = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0,
+         off_acc = 0;
   size_t total = 0;
   size_t state() const { return fbytes + gbytes; }
 };
@@ -377,6 +378,7 @@ AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp) {
   a.off_div = o; o = align_up(o + N * cs);
   a.off_ueq = o; o = align_up(o + 3 * N * cs);
   a.off_du = o; o = align_up(o + 3 * N * cs);
+  a.off_ureal = o; o = align_up(o + 3 * N * cs);
   a.off_gadj = o; o = align_up(o + 2 * P * cs);
   a.off_ax = o; o = align_up(o + 2 * P * cs);
   a.off_ay = o; o = align_up(o + 2 * P * cs);
@@ -446,6 +448,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   C* a_div = (C*)(b + a.off_div);
   C* a_ueq = (C*)(b + a.off_ueq);
   C* a_du = (C*)(b + a.off_du);
+  C* ureal = (C*)(b + a.off_ureal);
   C* gadj = (C*)(b + a.off_gadj);
   C* ax = (C*)(b + a.off_ax);
   C* ay = (C*)(b + a.off_ay);
@@ -493,11 +496,12 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
     for (int j = 1; j < len; ++j) HIPCHK(ctx, I::step_from(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j)));
     for (int j = len - 1; j >= 0; --j) {
       const S* gnext = j + 1 < len ? sg_g(j + 1) : (k + 1 < a.nseg ? ck_g(k + 1) : (const S*)ctx->gA);
-      HIPCHK(ctx, I::prepass_on(ctx, sg_f(j), sg_g(j)));
+      HIPCHK(ctx, I::prepass_on(ctx, sg_f(j), sg_g(j), ureal));
       const int nx = 1 - cur;
       hipLaunchKernelGGL(k_adj_collide<S>, dim3(nb), dim3(256), 0, st, (const C*)lf[cur], (const C*)lg[cur],
                          (const S*)sg_g(j), gnext, (const C*)ctx->rho, (const C*)ctx->T, (const C*)ctx->ueq,
-                         (const C*)ctx->du, lf[nx], lg[nx], a_rho, a_T, a_ueq, a_du, a_div, geo, ph);
+                         (const C*)ctx->du, (const C*)ureal, lf[nx], lg[nx], a_rho, a_T, a_ueq, a_du, a_div, geo,
+                         ph);
       hipLaunchKernelGGL(k_adj_velocity<C>, dim3(nb), dim3(256), 0, st, lf[nx], (const C*)a_div, a_ueq, a_du,
                          a_rho, (const C*)ctx->rho, (const C*)ctx->ueq, (const C*)ctx->du, geo);
       if (walls)
