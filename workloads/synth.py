@@ -188,6 +188,19 @@ def saturated_heat_transfer(nx=10, ny=10, nz=200, W=5.0, Tsat=0.86, Th=1.0, lam_
     return w
 
 
+def heated_surface(nx=160, ny=160, nz=100, diameter=70.0, W=5.0, Tsat=0.86, Tw=0.8931, theta_deg=120.0,
+                   steps=20000):
+    """Droplet on a heated surface (Sec. 4.3 set-up): a hemisphere of the given
+    diameter centred on the z = 0 wall, droplet and vapour at Tsat*Tc, wall
+    at Tw*Tc, outlet on top held at Tsat*Tc, periodic sides, wetting ghost
+    layer with kappa_w = tan(pi/2 - theta)."""
+    w = heated_wall(nx=nx, ny=ny, nz=nz, R0=diameter / 2.0, W=W, Tsat=Tsat, Tw_factor=Tw / Tsat, steps=steps,
+                    kappa_w=float(np.tan(np.pi / 2.0 - np.radians(theta_deg))))
+    w["name"] = "heated_surface"
+    w["T0"] = np.full(w["rho0"].shape, Tsat * w["Tc"])
+    return w
+
+
 def _poisson(lam: float, u: float) -> int:
     """Inverse-CDF Poisson draw from one uniform number."""
     k = 0
