@@ -125,11 +125,12 @@ __device__ __forceinline__ C psi_at(const C* __restrict__ psi, const Geom& g, C 
   return psi[cell_index(g, x, y, zi)] + sqrt(dx * dx + dy * dy) * kappa_w;
 }
 
-// Real velocity u = u_eq + du/2 at (x, y, z) within one cell of the domain:
-// 0 beyond walls, copy beyond pressure faces, wrap if periodic.
+// Real velocity of eq. (5) at (x, y, z) within one cell of the domain, from
+// the field k_force stores: 0 beyond walls, copy beyond pressure faces, wrap
+// if periodic.
 template <typename C>
-__device__ __forceinline__ void u_at(const C* __restrict__ ueq, const C* __restrict__ du, const Geom& g,
-                                     int x, int y, int z, C& ux, C& uy, C& uz) {
+__device__ __forceinline__ void u_real_at(const C* __restrict__ ureal, const Geom& g, int x, int y, int z, C& ux,
+                                          C& uy, C& uz) {
   x = resolve_open(x, g.nx, g.face[0]);
   y = resolve_open(y, g.ny, g.face[2]);
   if (z < 0 || z >= g.nz) {
@@ -141,10 +142,9 @@ __device__ __forceinline__ void u_at(const C* __restrict__ ueq, const C* __restr
     z = resolve_open(z, g.nz, g.face[4]);
   }
   const long long c = cell_index(g, x, y, z);
-  const long long N = g.N;
-  ux = ueq[c] + C(0.5) * du[c];
-  uy = ueq[c + N] + C(0.5) * du[c + N];
-  uz = ueq[c + 2 * N] + C(0.5) * du[c + 2 * N];
+  ux = ureal[c];
+  uy = ureal[c + g.N];
+  uz = ureal[c + 2 * g.N];
 }
 
 // ---------------------------------------------------------------- kernels
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(256) k_force(S* __restrict__ fpop, const typen
   du[c] = dux;
   du[c + g.N] = duy;
   du[c + 2 * g.N] = duz;
-  if (ureal) {  // the real velocity of eq. (5), in the operation order of u_at
+  {  // the real velocity of eq. (5), in the operation order of u_at
     ureal[c] = ux + C(0.5) * dux;
     ureal[c + g.N] = uy + C(0.5) * duy;
     ureal[c + 2 * g.N] = uz + C(0.5) * duz;
@@ -352,6 +352,7 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
                                                       const typename Storage<S>::C* __restrict__ T_f,
                                                       const typename Storage<S>::C* __restrict__ ueq,
                                                       const typename Storage<S>::C* __restrict__ du,
+                                                      const typename Storage<S>::C* __restrict__ ureal,
                                                       const typename Storage<S>::C* __restrict__ Th1,
                                                       typename Storage<S>::C* __restrict__ Th2, int corr, Geom g,
                                                       Phys<typename Storage<S>::C> ph) {
@@ -371,7 +372,7 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
 #pragma unroll
   for (int i = 1; i < 19; ++i) {
     C vx, vy, vz;
-    u_at(ueq, du, g, x + CX[i], y + CY[i], z + CZ[i], vx, vy, vz);
+    u_real_at(ureal, g, x + CX[i], y + CY[i], z + CZ[i], vx, vy, vz);
     div += C(3) * w19<C>(i) * (C(CX[i]) * vx + C(CY[i]) * vy + C(CZ[i]) * vz);
   }
   C gp[7];

@@ -55,6 +55,7 @@ struct lbm_ctx {
   void* psi = nullptr;
   void* ueq = nullptr;
   void* du = nullptr;
+  void* ureal = nullptr;             // real velocity of eq. (5), written by the prepass
   void* Th[2] = {nullptr, nullptr};  // S1 temperatures of the last two steps (vartheta = 1)
   int hist = 0;                      // how many of them are valid
   double* Tw[2] = {nullptr, nullptr};
@@ -77,8 +78,8 @@ long long ncells(const lbm_params& p) { return (long long)p.nx * p.ny * p.nz; }
 
 struct Layout {
   size_t state = 0, scratch = 0;
-  size_t off_fA, off_gA, off_fB, off_gB, off_rho, off_T, off_psi, off_ueq, off_du, off_Th0, off_Th1, off_Tw0, off_Tw1,
-      off_part, off_sums, off_flag, off_stage;
+  size_t off_fA, off_gA, off_fB, off_gB, off_rho, off_T, off_psi, off_ueq, off_du, off_ureal, off_Th0, off_Th1,
+      off_Tw0, off_Tw1, off_part, off_sums, off_flag, off_stage;
 };
 
 Layout layout_of(const lbm_params& p) {
@@ -96,6 +97,7 @@ Layout layout_of(const lbm_params& p) {
   L.off_psi = o; o = align_up(o + N * cs);
   L.off_ueq = o; o = align_up(o + 3 * N * cs);
   L.off_du = o; o = align_up(o + 3 * N * cs);
+  L.off_ureal = o; o = align_up(o + 3 * N * cs);
   const size_t nh = p.theta_corr ? N : 0;  // temperature history for vartheta = 1
   L.off_Th0 = o; o = align_up(o + nh * cs);
   L.off_Th1 = o; o = align_up(o + nh * cs);
@@ -232,7 +234,7 @@ struct Impl {
 
   // S0-S5 on the state (f, g): complete its boundary nodes in place and fill
   // rho, T, psi, u_eq, du.
-  static hipError_t prepass_on(lbm_ctx* ctx, S* f, S* g, C* ureal = nullptr) {
+  static hipError_t prepass_on(lbm_ctx* ctx, S* f, S* g) {
     const lbm_params& p = ctx->p;
     const Geom geo = geom_of(p);
     const Phys<C> ph = phys_of<C>(p);
@@ -243,7 +245,7 @@ struct Impl {
     hipLaunchKernelGGL(k_macro<S>, dim3(nb), dim3(256), 0, ctx->stream, f, g, (C*)ctx->rho, (C*)ctx->T,
                        (C*)ctx->psi, ctx->flag, geo, fc, ph);
     hipLaunchKernelGGL(k_force<S>, dim3(nb), dim3(256), 0, ctx->stream, f, (const C*)ctx->rho,
-                       (const C*)ctx->psi, (C*)ctx->ueq, (C*)ctx->du, ureal, geo, fc, ph);
+                       (const C*)ctx->psi, (C*)ctx->ueq, (C*)ctx->du, (C*)ctx->ureal, geo, fc, ph);
     return hipGetLastError();
   }
 
@@ -260,7 +262,8 @@ struct Impl {
     const int corr = ctx->p.theta_corr ? (ctx->hist >= 2 ? 2 : 1) : 0;
     hipLaunchKernelGGL(k_collide_push<S>, dim3(blocks_for(geo.N)), dim3(256), 0, ctx->stream, (const S*)fs,
                        (const S*)gs, fd, gd, (const C*)ctx->rho, (const C*)ctx->T, (const C*)ctx->ueq,
-                       (const C*)ctx->du, (const C*)ctx->Th[0], (C*)ctx->Th[1], corr, geo, phys_of<C>(ctx->p));
+                       (const C*)ctx->du, (const C*)ctx->ureal, (const C*)ctx->Th[0], (C*)ctx->Th[1], corr, geo,
+                       phys_of<C>(ctx->p));
     if (corr) {
       std::swap(ctx->Th[0], ctx->Th[1]);
       ctx->hist = std::min(ctx->hist + 1, 2);
@@ -348,8 +351,7 @@ struct AdjPlan {
   int nsteps = 0, nseg = 0, L = 0;
   size_t fbytes = 0, gbytes = 0;
   size_t off_ck = 0, off_seg = 0, off_lf[2] = {0, 0}, off_lg[2] = {0, 0}, off_rho = 0, off_T = 0, off_div = 0,
-         off_ueq = 0, off_du = 0, off_ureal = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0,
-         off_acc = 0;
+         off_ueq = 0, off_du = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0, off_acc = 0;
   size_t total = 0;
   size_t state() const { return fbytes + gbytes; }
 };
@@ -378,7 +380,6 @@ AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp) {
   a.off_div = o; o = align_up(o + N * cs);
   a.off_ueq = o; o = align_up(o + 3 * N * cs);
   a.off_du = o; o = align_up(o + 3 * N * cs);
-  a.off_ureal = o; o = align_up(o + 3 * N * cs);
   a.off_gadj = o; o = align_up(o + 2 * P * cs);
   a.off_ax = o; o = align_up(o + 2 * P * cs);
   a.off_ay = o; o = align_up(o + 2 * P * cs);
@@ -448,7 +449,6 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   C* a_div = (C*)(b + a.off_div);
   C* a_ueq = (C*)(b + a.off_ueq);
   C* a_du = (C*)(b + a.off_du);
-  C* ureal = (C*)(b + a.off_ureal);
   C* gadj = (C*)(b + a.off_gadj);
   C* ax = (C*)(b + a.off_ax);
   C* ay = (C*)(b + a.off_ay);
@@ -496,12 +496,12 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
     for (int j = 1; j < len; ++j) HIPCHK(ctx, I::step_from(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j)));
     for (int j = len - 1; j >= 0; --j) {
       const S* gnext = j + 1 < len ? sg_g(j + 1) : (k + 1 < a.nseg ? ck_g(k + 1) : (const S*)ctx->gA);
-      HIPCHK(ctx, I::prepass_on(ctx, sg_f(j), sg_g(j), ureal));
+      HIPCHK(ctx, I::prepass_on(ctx, sg_f(j), sg_g(j)));
       const int nx = 1 - cur;
       hipLaunchKernelGGL(k_adj_collide<S>, dim3(nb), dim3(256), 0, st, (const C*)lf[cur], (const C*)lg[cur],
                          (const S*)sg_g(j), gnext, (const C*)ctx->rho, (const C*)ctx->T, (const C*)ctx->ueq,
-                         (const C*)ctx->du, (const C*)ureal, lf[nx], lg[nx], a_rho, a_T, a_ueq, a_du, a_div, geo,
-                         ph);
+                         (const C*)ctx->du, (const C*)ctx->ureal, lf[nx], lg[nx], a_rho, a_T, a_ueq, a_du, a_div,
+                         geo, ph);
       hipLaunchKernelGGL(k_adj_velocity<C>, dim3(nb), dim3(256), 0, st, lf[nx], (const C*)a_div, a_ueq, a_du,
                          a_rho, (const C*)ctx->rho, (const C*)ctx->ueq, (const C*)ctx->du, geo);
       if (walls)
@@ -596,7 +596,7 @@ lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_by
   char* b = ctx->base;
   ctx->fA = b + L.off_fA; ctx->gA = b + L.off_gA; ctx->fB = b + L.off_fB; ctx->gB = b + L.off_gB;
   ctx->rho = b + L.off_rho; ctx->T = b + L.off_T; ctx->psi = b + L.off_psi;
-  ctx->ueq = b + L.off_ueq; ctx->du = b + L.off_du;
+  ctx->ueq = b + L.off_ueq; ctx->du = b + L.off_du; ctx->ureal = b + L.off_ureal;
   ctx->Th[0] = b + L.off_Th0; ctx->Th[1] = b + L.off_Th1;
   ctx->Tw[0] = (double*)(b + L.off_Tw0); ctx->Tw[1] = (double*)(b + L.off_Tw1);
   ctx->partials = (double*)(b + L.off_part);
