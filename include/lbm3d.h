@@ -189,7 +189,11 @@ typedef struct {
   int32_t wall_face;      /* 4 (-z) or 5 (+z) */
 } lbm_adjoint_spec;
 
-/* Device bytes lbm_adjoint allocates for spec on this context. */
+/* Device bytes lbm_adjoint allocates for spec on this context: K + L
+ * stored states, two adjoint states and a few fields; when the step runs on
+ * the unfused kernels also the per-cell fields (rho, T, psi, three
+ * velocities of three components) of the L states of a segment, kept from
+ * its recomputation so that the reverse step does not derive them again. */
 lbm_status lbm_adjoint_bytes(const lbm_ctx* ctx, const lbm_adjoint_spec* spec, size_t* bytes);
 
 lbm_status lbm_adjoint(lbm_ctx* ctx, const lbm_adjoint_spec* spec, double* J, double* dJ_dTw, double* dJ_dkappa,

@@ -76,6 +76,14 @@ namespace {
 
 long long ncells(const lbm_params& p) { return (long long)p.nx * p.ny * p.nz; }
 
+// The per-cell fields of one state in the compute precision: rho, T, psi,
+// u_eq = j/rho, Delta u = F/rho and the real velocity of eq. (5)
+struct FieldSet {
+  void *rho, *T, *psi, *ueq, *du, *ureal;
+};
+
+FieldSet ctx_fields(const lbm_ctx* ctx) { return {ctx->rho, ctx->T, ctx->psi, ctx->ueq, ctx->du, ctx->ureal}; }
+
 struct Layout {
   size_t state = 0, scratch = 0;
   size_t off_fA, off_gA, off_fB, off_gB, off_rho, off_T, off_psi, off_ueq, off_du, off_ureal, off_Th0, off_Th1,
@@ -234,7 +242,9 @@ struct Impl {
 
   // S0-S5 on the state (f, g): complete its boundary nodes in place and fill
   // rho, T, psi, u_eq, du.
-  static hipError_t prepass_on(lbm_ctx* ctx, S* f, S* g) {
+  // S0-S5 of the state (f, g) into the field set F: Dirichlet completion of g
+  // in place, then rho, T, psi and the velocities
+  static hipError_t prepass_to(lbm_ctx* ctx, S* f, S* g, const FieldSet& F) {
     const lbm_params& p = ctx->p;
     const Geom geo = geom_of(p);
     const Phys<C> ph = phys_of<C>(p);
@@ -242,33 +252,38 @@ struct Impl {
     const unsigned nb = blocks_for(geo.N);
     hipError_t e = thermal_dirichlet(ctx, g);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_macro<S>, dim3(nb), dim3(256), 0, ctx->stream, f, g, (C*)ctx->rho, (C*)ctx->T,
-                       (C*)ctx->psi, ctx->flag, geo, fc, ph);
-    hipLaunchKernelGGL(k_force<S>, dim3(nb), dim3(256), 0, ctx->stream, f, (const C*)ctx->rho,
-                       (const C*)ctx->psi, (C*)ctx->ueq, (C*)ctx->du, (C*)ctx->ureal, geo, fc, ph);
+    hipLaunchKernelGGL(k_macro<S>, dim3(nb), dim3(256), 0, ctx->stream, f, g, (C*)F.rho, (C*)F.T, (C*)F.psi,
+                       ctx->flag, geo, fc, ph);
+    hipLaunchKernelGGL(k_force<S>, dim3(nb), dim3(256), 0, ctx->stream, f, (const C*)F.rho, (const C*)F.psi,
+                       (C*)F.ueq, (C*)F.du, (C*)F.ureal, geo, fc, ph);
     return hipGetLastError();
   }
+
+  static hipError_t prepass_on(lbm_ctx* ctx, S* f, S* g) { return prepass_to(ctx, f, g, ctx_fields(ctx)); }
 
   static hipError_t prepass(lbm_ctx* ctx) { return prepass_on(ctx, (S*)ctx->fA, (S*)ctx->gA); }
 
   // One step from the state (fs, gs) into (fd, gd).  The unfused kernels
   // complete the boundary nodes of (fs, gs) in place; the fused kernel only
   // reads it.
-  static hipError_t step_ref(lbm_ctx* ctx, S* fs, S* gs, S* fd, S* gd) {
-    hipError_t e = prepass_on(ctx, fs, gs);
+  static hipError_t step_ref_to(lbm_ctx* ctx, S* fs, S* gs, S* fd, S* gd, const FieldSet& F) {
+    hipError_t e = prepass_to(ctx, fs, gs, F);
     if (e != hipSuccess) return e;
     const Geom geo = geom_of(ctx->p);
     // vartheta = 1: record T, and apply the correction once two past values exist
     const int corr = ctx->p.theta_corr ? (ctx->hist >= 2 ? 2 : 1) : 0;
     hipLaunchKernelGGL(k_collide_push<S>, dim3(blocks_for(geo.N)), dim3(256), 0, ctx->stream, (const S*)fs,
-                       (const S*)gs, fd, gd, (const C*)ctx->rho, (const C*)ctx->T, (const C*)ctx->ueq,
-                       (const C*)ctx->du, (const C*)ctx->ureal, (const C*)ctx->Th[0], (C*)ctx->Th[1], corr, geo,
-                       phys_of<C>(ctx->p));
+                       (const S*)gs, fd, gd, (const C*)F.rho, (const C*)F.T, (const C*)F.ueq, (const C*)F.du,
+                       (const C*)F.ureal, (const C*)ctx->Th[0], (C*)ctx->Th[1], corr, geo, phys_of<C>(ctx->p));
     if (corr) {
       std::swap(ctx->Th[0], ctx->Th[1]);
       ctx->hist = std::min(ctx->hist + 1, 2);
     }
     return hipGetLastError();
+  }
+
+  static hipError_t step_ref(lbm_ctx* ctx, S* fs, S* gs, S* fd, S* gd) {
+    return step_ref_to(ctx, fs, gs, fd, gd, ctx_fields(ctx));
   }
 
   static hipError_t step_fused(lbm_ctx* ctx, const S* fs, const S* gs, S* fd, S* gd) {
@@ -352,11 +367,19 @@ struct AdjPlan {
   size_t fbytes = 0, gbytes = 0;
   size_t off_ck = 0, off_seg = 0, off_lf[2] = {0, 0}, off_lg[2] = {0, 0}, off_rho = 0, off_T = 0, off_div = 0,
          off_ueq = 0, off_du = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0, off_acc = 0;
+  // fields of every state of a segment, kept from its recomputation (unfused
+  // steps only; the fused kernel writes no fields)
+  bool cache = false;
+  size_t off_fields = 0, fslot = 0, fN = 0;
   size_t total = 0;
   size_t state() const { return fbytes + gbytes; }
+  FieldSet fields(char* base, int j) const {
+    char* q = base + off_fields + (size_t)j * fslot;
+    return {q, q + fN, q + 2 * fN, q + 3 * fN, q + 6 * fN, q + 9 * fN};
+  }
 };
 
-AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp) {
+AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp, bool cache_fields) {
   AdjPlan a;
   a.nsteps = sp.nsteps;
   int K = sp.n_checkpoints > 0 ? sp.n_checkpoints : (int)std::ceil(std::sqrt((double)sp.nsteps));
@@ -386,6 +409,12 @@ AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp) {
   a.off_kap = o; o = align_up(o + 2 * P * 8);
   a.off_grad = o; o = align_up(o + P * 8);
   a.off_acc = o; o = align_up(o + 64);
+  a.cache = cache_fields;
+  if (a.cache) {
+    a.fN = N * cs;
+    a.fslot = align_up(12 * a.fN);
+    a.off_fields = o; o += (size_t)a.L * a.fslot;
+  }
   a.total = o;
   return a;
 }
@@ -423,7 +452,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   using C = typename Storage<S>::C;
   using I = Impl<S>;
   const lbm_params& p = ctx->p;
-  const AdjPlan a = adjoint_plan(p, sp);
+  const AdjPlan a = adjoint_plan(p, sp, !ctx->fused_ok);
   const Geom geo = geom_of(p);
   const long long N = geo.N;
   const long long P = (long long)p.nx * p.ny;
@@ -493,23 +522,32 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
     const int len = std::min(a.L, a.nsteps - k * a.L);
     HIPCHK(ctx, hipMemcpyAsync(sg_f(0), ck_f(k), fsz, hipMemcpyDeviceToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(sg_g(0), ck_g(k), gsz, hipMemcpyDeviceToDevice, st));
-    for (int j = 1; j < len; ++j) HIPCHK(ctx, I::step_from(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j)));
+    // recompute the segment; unfused steps keep the fields of every state
+    for (int j = 1; j < len; ++j) {
+      if (a.cache) HIPCHK(ctx, I::step_ref_to(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j), a.fields(b, j - 1)));
+      else HIPCHK(ctx, I::step_from(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j)));
+    }
     for (int j = len - 1; j >= 0; --j) {
       const S* gnext = j + 1 < len ? sg_g(j + 1) : (k + 1 < a.nseg ? ck_g(k + 1) : (const S*)ctx->gA);
-      HIPCHK(ctx, I::prepass_on(ctx, sg_f(j), sg_g(j)));
+      const FieldSet F = a.cache ? a.fields(b, j) : ctx_fields(ctx);
+      if (!a.cache || j == len - 1) HIPCHK(ctx, I::prepass_to(ctx, sg_f(j), sg_g(j), F));
+      const C* rho = (const C*)F.rho;
+      const C* T = (const C*)F.T;
+      const C* psi = (const C*)F.psi;
+      const C* ueq = (const C*)F.ueq;
+      const C* du = (const C*)F.du;
       const int nx = 1 - cur;
       hipLaunchKernelGGL(k_adj_collide<S>, dim3(nb), dim3(256), 0, st, (const C*)lf[cur], (const C*)lg[cur],
-                         (const S*)sg_g(j), gnext, (const C*)ctx->rho, (const C*)ctx->T, (const C*)ctx->ueq,
-                         (const C*)ctx->du, (const C*)ctx->ureal, lf[nx], lg[nx], a_rho, a_T, a_ueq, a_du, a_div,
-                         geo, ph);
+                         (const S*)sg_g(j), gnext, rho, T, ueq, du, (const C*)F.ureal, lf[nx], lg[nx], a_rho, a_T,
+                         a_ueq, a_du, a_div, geo, ph);
       hipLaunchKernelGGL(k_adj_velocity<C>, dim3(nb), dim3(256), 0, st, lf[nx], (const C*)a_div, a_ueq, a_du,
-                         a_rho, (const C*)ctx->rho, (const C*)ctx->ueq, (const C*)ctx->du, geo);
+                         a_rho, rho, ueq, du, geo);
       if (walls)
-        hipLaunchKernelGGL(k_adj_ghost<C>, dim3(npb), dim3(256), 0, st, (const C*)a_du, (const C*)ctx->psi, gadj, ax,
-                           ay, kap, geo, ph);
+        hipLaunchKernelGGL(k_adj_ghost<C>, dim3(npb), dim3(256), 0, st, (const C*)a_du, psi, gadj, ax, ay, kap, geo,
+                           ph);
       hipLaunchKernelGGL(k_adj_psi<C>, dim3(nb), dim3(256), 0, st, lf[nx], lg[nx], (const C*)a_rho,
-                         (const C*)a_T, (const C*)a_ueq, (const C*)a_du, (const C*)ctx->psi, (const C*)ctx->rho,
-                         (const C*)ctx->T, (const C*)gadj, (const C*)ax, (const C*)ay, geo, ph);
+                         (const C*)a_T, (const C*)a_ueq, (const C*)a_du, psi, rho, T, (const C*)gadj, (const C*)ax,
+                         (const C*)ay, geo, ph);
       hipLaunchKernelGGL(k_adj_dirichlet<C>, dim3(npb), dim3(256), 0, st, lg[nx], grad, (int)sp.wall_face, geo, ph);
       HIPCHK(ctx, hipGetLastError());
       cur = nx;
@@ -768,7 +806,7 @@ lbm_status lbm_adjoint_bytes(const lbm_ctx* ctx, const lbm_adjoint_spec* spec, s
   std::string msg;
   const lbm_status s = adjoint_check(ctx, spec, msg);
   if (s != LBM_OK) return s;
-  *bytes = adjoint_plan(ctx->p, *spec).total;
+  *bytes = adjoint_plan(ctx->p, *spec, !ctx->fused_ok).total;
   return LBM_OK;
 }
 
