@@ -299,8 +299,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     // with prefetch, fb/gc/hv/gv already hold plane p (taken in at the end of
     // the previous step); issue the loads of plane p+1, which complete while
     // planes p-1 and p-2 are updated.  In the steady march the halo loads
-    // are issued after the D3Q19 stores instead, so that those stores do not
-    // queue behind them
+    // are issued once plane p is in LDS: issued together with the tile's
+    // loads they delay the stores of the D3Q19 stage
     bool next_loaded = false;
     if constexpr (PF) {
       int zn;
@@ -384,6 +384,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     }
     __syncthreads();
     // ---------------------------------------------------------------- plane p-1: force, u, D3Q19
+    if constexpr (ST && PF) load_cell(p + 1, hcolb_pf, pfh);
     finish_pulls();
     const int q = p - 1;
     int zq;
@@ -463,7 +464,6 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           }
         }
       }
-      if constexpr (ST && PF) load_cell(p + 1, hcolb_pf, pfh);
       if (has_ring) {
         // u vanishes on wall nodes; elsewhere the same operation order as the
         // tile's own u, so that u does not depend on which thread evaluates it
