@@ -113,8 +113,9 @@ typedef struct {
 lbm_status lbm_default_params(lbm_params* p, int32_t nx, int32_t ny, int32_t nz);
 
 /* Bytes of device memory a context needs: state_bytes for the two copies of
- * the populations (2 * 26 * cells * element size), scratch_bytes for fields,
- * wall temperature planes and reduction partials.  Validates *p. */
+ * the populations (2 * 26 * nz * (nx*ny + 64) * element size: each direction
+ * plane is padded by 64 elements), scratch_bytes for fields, wall
+ * temperature planes and reduction partials.  Validates *p. */
 lbm_status lbm_required_bytes(const lbm_params* p, size_t* state_bytes, size_t* scratch_bytes);
 
 /* Create a context on the current HIP device.  device_buffer: NULL lets the

@@ -47,6 +47,7 @@ struct FusedArgs {
   Phys<C> ph;
   int nx, ny, nz;
   long long N;
+  long long pitch;  // elements from one direction plane to the next
   int zwall;  // 1: no-slip walls at z = 0 and z = nz - 1; 0: periodic z
   int tiles_x, ntiles, chunk;
   int xcd_blocks;  // 1: each XCD owns a 2 x 4 block of the tile grid
@@ -164,12 +165,12 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   const int z0 = chunk * a.chunk, z1 = min(a.nz, z0 + a.chunk);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long long N = a.N;
-  const long long PS = (long long)nx * ny;
+  const long long PS = a.pitch;  // population planes: direction i of level z starts at (z*Q + i)*PS
   const int x = x0 + tx, y = y0 + ty;
   constexpr unsigned ES = sizeof(S);
   const unsigned col = (unsigned)(x + nx * y);
   const unsigned colb = col * ES;
-  const unsigned PB = (unsigned)(nx * ny) * ES;  // bytes of one plane of one direction
+  const unsigned PB = (unsigned)a.pitch * ES;  // bytes from one direction plane to the next
   const unsigned F19 = 19 * PB, G7 = 7 * PB;       // bytes of all directions of one plane
   // byte offsets from this column to its periodic x / y neighbours in a plane
   const int dxm = (wrapn(x - 1, nx) - x) * (int)ES, dxp = (wrapn(x + 1, nx) - x) * (int)ES;
@@ -626,6 +627,7 @@ struct FusedImpl {
     a.ny = p.ny;
     a.nz = p.nz;
     a.N = (long long)p.nx * p.ny * p.nz;
+    a.pitch = plane_pitch(p.nx, p.ny);
     a.zwall = p.face[4] == LBM_FACE_WALL;
     const int TY = fused_tile_height(p.precision);
     a.tiles_x = p.nx / FTX;

@@ -20,13 +20,20 @@ struct Geom {
   int nx, ny, nz;
   int face[6];
   long long N;
+  long long pitch;  // elements from one direction plane to the next
 };
 
 // Device layout of the populations: plane-major structure of arrays.
 // Population i of cell (x, y, z) of a Q-velocity lattice is element
-// (z*Q + i)*nx*ny + x + nx*y, so one plane of one direction is contiguous.
+// (z*Q + i)*pitch + x + nx*y, so one plane of one direction is contiguous.
+// The pitch is nx*ny plus kPlanePad elements: with an unpadded power-of-two
+// plane the 26 direction planes of a z level start at the same offset modulo
+// large powers of two and their streams crowd the same memory channels.
+constexpr long long kPlanePad = 64;
+__host__ __device__ inline long long plane_pitch(int nx, int ny) { return (long long)nx * ny + kPlanePad; }
+
 __device__ __forceinline__ long long pidx(const Geom& g, int Q, int i, int x, int y, int z) {
-  return ((long long)z * Q + i) * ((long long)g.nx * g.ny) + x + (long long)g.nx * y;
+  return ((long long)z * Q + i) * g.pitch + x + (long long)g.nx * y;
 }
 
 template <typename C>
@@ -445,23 +452,22 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_init(S* __restrict__ fpop, S* __restrict__ gpop,
                                               const double* __restrict__ rho, const double* __restrict__ u,
                                               const double* __restrict__ T, long long c0, long long len,
-                                              long long N, int nz, double rho_ref, double T_ref, double w0,
-                                              double w1) {
+                                              long long PS, long long pitch, double rho_ref, double T_ref,
+                                              double w0, double w1) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= len) return;
   const long long c = c0 + t;
-  const long long PS = N / nz;
   const long long zc = c / PS, xy = c - zc * PS;
   const double r = rho[t];
   const double vx = u ? u[t] : 0.0, vy = u ? u[t + len] : 0.0, vz = u ? u[t + 2 * len] : 0.0;
 #pragma unroll
   for (int i = 0; i < 19; ++i)
-    Storage<S>::store(fpop + (zc * 19 + i) * PS + xy,
+    Storage<S>::store(fpop + (zc * 19 + i) * pitch + xy,
                       (typename Storage<S>::C)feq19_dev<double>(i, r, rho_ref, vx, vy, vz));
   const double dT = T[t] - T_ref;
 #pragma unroll
   for (int i = 0; i < 7; ++i)
-    Storage<S>::store(gpop + (zc * 7 + i) * PS + xy, (typename Storage<S>::C)((i == 0 ? w0 : w1) * dT));
+    Storage<S>::store(gpop + (zc * 7 + i) * pitch + xy, (typename Storage<S>::C)((i == 0 ? w0 : w1) * dT));
 }
 
 template <typename C>
@@ -485,22 +491,21 @@ __global__ void __launch_bounds__(256) k_fields_out(const C* __restrict__ rho, c
 template <typename S>
 __global__ void __launch_bounds__(256) k_pops_out(const S* __restrict__ fpop, const S* __restrict__ gpop,
                                                   double* __restrict__ of, double* __restrict__ og,
-                                                  long long c0, long long len, long long N, int nz,
+                                                  long long c0, long long len, long long PS, long long pitch,
                                                   double rho_ref, double T_ref, double w0, double w1) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= len) return;
   const long long c = c0 + t;
-  const long long PS = N / nz;
   const long long zc = c / PS, xy = c - zc * PS;
   if (of) {
 #pragma unroll
     for (int i = 0; i < 19; ++i)
-      of[t + i * len] = (double)Storage<S>::load(fpop + (zc * 19 + i) * PS + xy) + w19<double>(i) * rho_ref;
+      of[t + i * len] = (double)Storage<S>::load(fpop + (zc * 19 + i) * pitch + xy) + w19<double>(i) * rho_ref;
   }
   if (og) {
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-      og[t + i * len] = (double)Storage<S>::load(gpop + (zc * 7 + i) * PS + xy) + (i == 0 ? w0 : w1) * T_ref;
+      og[t + i * len] = (double)Storage<S>::load(gpop + (zc * 7 + i) * pitch + xy) + (i == 0 ? w0 : w1) * T_ref;
   }
 }
 

@@ -95,10 +95,11 @@ Layout layout_of(const lbm_params& p) {
   const size_t N = (size_t)ncells(p);
   const size_t es = elem_size(p.precision), cs = compute_size(p.precision);
   size_t o = 0;
-  L.off_fA = o; o = align_up(o + 19 * N * es);
-  L.off_gA = o; o = align_up(o + 7 * N * es);
-  L.off_fB = o; o = align_up(o + 19 * N * es);
-  L.off_gB = o; o = align_up(o + 7 * N * es);
+  const size_t NP = (size_t)p.nz * plane_pitch(p.nx, p.ny);  // population slots per direction
+  L.off_fA = o; o = align_up(o + 19 * NP * es);
+  L.off_gA = o; o = align_up(o + 7 * NP * es);
+  L.off_fB = o; o = align_up(o + 19 * NP * es);
+  L.off_gB = o; o = align_up(o + 7 * NP * es);
   L.state = o;
   L.off_rho = o; o = align_up(o + N * cs);
   L.off_T = o; o = align_up(o + N * cs);
@@ -196,6 +197,7 @@ Geom geom_of(const lbm_params& p) {
   g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
   for (int k = 0; k < 6; ++k) g.face[k] = p.face[k];
   g.N = ncells(p);
+  g.pitch = plane_pitch(p.nx, p.ny);
   return g;
 }
 
@@ -308,7 +310,8 @@ struct Impl {
                               long long len) {
     const lbm_params& p = ctx->p;
     hipLaunchKernelGGL(k_init<S>, dim3(blocks_for(len)), dim3(256), 0, ctx->stream, (S*)ctx->fA, (S*)ctx->gA, drho,
-                       du, dT, c0, len, ncells(p), p.nz, p.rho_ref, p.T_ref, 1.0 - p.wbar, p.wbar / 6.0);
+                       du, dT, c0, len, (long long)p.nx * p.ny, plane_pitch(p.nx, p.ny), p.rho_ref, p.T_ref,
+                       1.0 - p.wbar, p.wbar / 6.0);
     return hipGetLastError();
   }
 
@@ -323,8 +326,8 @@ struct Impl {
   static hipError_t pops_slab(lbm_ctx* ctx, double* of, double* og, long long c0, long long len) {
     const lbm_params& p = ctx->p;
     hipLaunchKernelGGL(k_pops_out<S>, dim3(blocks_for(len)), dim3(256), 0, ctx->stream, (const S*)ctx->fA,
-                       (const S*)ctx->gA, of, og, c0, len, ncells(p), p.nz, p.rho_ref, p.T_ref, 1.0 - p.wbar,
-                       p.wbar / 6.0);
+                       (const S*)ctx->gA, of, og, c0, len, (long long)p.nx * p.ny, plane_pitch(p.nx, p.ny),
+                       p.rho_ref, p.T_ref, 1.0 - p.wbar, p.wbar / 6.0);
     return hipGetLastError();
   }
 
@@ -389,14 +392,15 @@ AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp, bool cache
   const size_t N = (size_t)ncells(p);
   const size_t P = (size_t)p.nx * p.ny;
   const size_t es = elem_size(p.precision), cs = compute_size(p.precision);
-  a.fbytes = align_up(19 * N * es);
-  a.gbytes = align_up(7 * N * es);
+  const size_t NP = (size_t)p.nz * plane_pitch(p.nx, p.ny);
+  a.fbytes = align_up(19 * NP * es);
+  a.gbytes = align_up(7 * NP * es);
   size_t o = 0;
   a.off_ck = o; o += (size_t)a.nseg * a.state();
   a.off_seg = o; o += (size_t)a.L * a.state();
   for (int k = 0; k < 2; ++k) {
-    a.off_lf[k] = o; o = align_up(o + 19 * N * cs);
-    a.off_lg[k] = o; o = align_up(o + 7 * N * cs);
+    a.off_lf[k] = o; o = align_up(o + 19 * NP * cs);
+    a.off_lg[k] = o; o = align_up(o + 7 * NP * cs);
   }
   a.off_rho = o; o = align_up(o + N * cs);
   a.off_T = o; o = align_up(o + N * cs);
@@ -485,7 +489,8 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   double* grad = (double*)(b + a.off_grad);
   double* acc = (double*)(b + a.off_acc);
   const hipStream_t st = ctx->stream;
-  const size_t fsz = 19 * (size_t)N * sizeof(S), gsz = 7 * (size_t)N * sizeof(S);
+  const size_t NP = (size_t)p.nz * plane_pitch(p.nx, p.ny);
+  const size_t fsz = 19 * NP * sizeof(S), gsz = 7 * NP * sizeof(S);
   const bool walls = p.face[4] == LBM_FACE_WALL || p.face[5] == LBM_FACE_WALL;
 
   // forward pass with checkpoints; J = M(t0) - M(t0 + N)

@@ -91,8 +91,10 @@ def test_required_bytes(prec, es):
     p = P.make_params(40, 30, 20, precision=prec)
     s, st, sc = _required(P, lib, p)
     assert s == 0
-    N = 40 * 30 * 20
-    assert st >= 2 * 26 * N * es and st < 2 * 26 * N * es + 4 * 256
+    # two states of 26 direction planes per z level, each plane padded to
+    # nx*ny + 64 elements, each buffer aligned to 256 bytes
+    slots = 20 * (40 * 30 + 64)
+    assert st >= 2 * 26 * slots * es and st < 2 * 26 * slots * es + 4 * 256
     assert sc > 0
 
 
