@@ -36,6 +36,8 @@
 namespace lbm {
 
 constexpr int FTX = 64;
+// D3Q19 directions pushed before the second barrier of a steady plane step
+constexpr int kEarlyF = 10;
 // cache policy of the population stores (2: non-temporal streaming stores)
 #ifndef LBM_STREAM_STORES
 #define LBM_STREAM_STORES 0
@@ -451,7 +453,14 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           S* pm = fB + PS * 19 * (lo_out ? nz - 1 : zq - 1);
           S* p0 = fB + PS * 19 * zq;
           S* pp = fB + PS * 19 * (hi_out ? 0 : zq + 1);
-          if (ST || !(a.zwall && (lo_out || hi_out))) {
+          if (ST) {
+            // steady march: the first kEarlyF directions here, the rest after
+            // the next barrier, so that the plane's stores reach memory in two
+            // smaller bursts
+#pragma unroll
+            for (int i = 0; i < kEarlyF; ++i)
+              st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+          } else if (!(a.zwall && (lo_out || hi_out))) {
 #pragma unroll
             for (int i = 0; i < 19; ++i)
               st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
@@ -483,6 +492,15 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       }
     }
     __syncthreads();
+    if constexpr (ST) {
+      // the remaining D3Q19 pushes of plane q = p-1 (interior planes: no wrap)
+      S* pm = fB + PS * 19 * (p - 2);
+      S* p0 = fB + PS * 19 * (p - 1);
+      S* pp = fB + PS * 19 * p;
+#pragma unroll
+      for (int i = kEarlyF; i < 19; ++i)
+        st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+    }
     // ---------------------------------------------------------------- divergence contributions of u(q)
     if (do_u) {
 #pragma unroll
