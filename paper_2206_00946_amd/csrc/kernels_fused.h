@@ -236,13 +236,19 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   // with 16 rows or FP64 the registers are not there and planes load in place
   constexpr bool PF = TY <= 8 && sizeof(C) == 4;
   C pfi[26], pfh[26];
-  auto load_cell = [&](int zn, unsigned off, C* l) {
+  auto load_f = [&](int zn, unsigned off, C* l) {
     const S* fz = fA + PS * 19 * zn;
-    const S* gz = gA + PS * 7 * zn;
 #pragma unroll
     for (int i = 0; i < 19; ++i) l[i] = ld_at(fz, F19, off, i * PB);
+  };
+  auto load_g = [&](int zn, unsigned off, C* l) {
+    const S* gz = gA + PS * 7 * zn;
 #pragma unroll
     for (int i = 0; i < 7; ++i) l[19 + i] = ld_at(gz, G7, off, i * PB);
+  };
+  auto load_cell = [&](int zn, unsigned off, C* l) {
+    load_f(zn, off, l);
+    load_g(zn, off, l);
   };
   // lanes without a halo cell load from beyond the descriptor range: the
   // hardware returns 0 without a memory access, and the load count stays
@@ -301,14 +307,15 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     }
     // with prefetch, fb/gc/hv/gv already hold plane p (taken in at the end of
     // the previous step); issue the loads of plane p+1, which complete while
-    // planes p-1 and p-2 are updated.  In the steady march the halo loads
-    // are issued once plane p is in LDS: issued together with the tile's
-    // loads they delay the stores of the D3Q19 stage
+    // planes p-1 and p-2 are updated.  In the steady march only the tile's
+    // f loads are issued here; the halo loads follow once plane p is in LDS
+    // and the tile's g loads after the second barrier, which spreads the
+    // step's memory traffic over its three stages
     bool next_loaded = false;
     if constexpr (PF) {
       int zn;
       if (ST) {
-        load_cell(p + 1, colb, pfi);
+        load_f(p + 1, colb, pfi);
         next_loaded = true;
       } else if (p < p_end && plane_of(p + 1, zn)) {
         prefetch(zn);
@@ -492,6 +499,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       }
     }
     __syncthreads();
+    if constexpr (ST && PF) load_g(p + 1, colb, pfi);
     if constexpr (ST) {
       // the remaining D3Q19 pushes of plane q = p-1 (interior planes: no wrap)
       S* pm = fB + PS * 19 * (p - 2);
