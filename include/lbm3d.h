@@ -159,6 +159,23 @@ lbm_status lbm_fields(lbm_ctx* ctx, double* rho, double* u, double* T, int32_t d
  * Host pointers; either may be NULL.  Synchronous. */
 lbm_status lbm_populations(lbm_ctx* ctx, double* f, double* g);
 
+/* Checkpoint and resume.  lbm_save writes the whole state of the context
+ * into host memory: the current populations in their device layout and
+ * storage format, the step counter, the initial mass (for evap_mass), the
+ * wall temperature planes set by lbm_set_wall_T, kappa_w and, with
+ * theta_corr = 1, the two stored temperatures of eq. (16).  lbm_load puts
+ * such an image into a context created with the same grid, precision and
+ * theta_corr (the context's other parameters apply from then on), after
+ * which lbm_step continues exactly as the saving context would have.
+ * lbm_save_bytes gives the image size.  Errors: LBM_EINVAL for a NULL
+ * pointer, a buffer smaller than the image, an image not written by
+ * lbm_save or one from a different grid, precision or theta_corr;
+ * LBM_ESTATE for lbm_save before lbm_init.  The caller owns the host
+ * buffer.  Synchronous. */
+lbm_status lbm_save_bytes(const lbm_ctx* ctx, size_t* bytes);
+lbm_status lbm_save(lbm_ctx* ctx, void* host_dst, size_t bytes);
+lbm_status lbm_load(lbm_ctx* ctx, const void* host_src, size_t bytes);
+
 /* FP64 diagnostics of the current state (mass, energy, liquid volume,
  * evaporated mass), reduced on the GPU in a fixed order.  Synchronous. */
 lbm_status lbm_reduce(lbm_ctx* ctx, lbm_diag* out);

@@ -569,6 +569,38 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   return LBM_OK;
 }
 
+// ---------------------------------------------------------------- checkpoint / resume
+
+// Host image of a context's state: this header, then the raw population
+// buffers A (f, then g, in the device layout and storage format), the two
+// temperature-history fields when theta_corr = 1, and the two wall
+// temperature planes.
+struct SaveHeader {
+  char magic[8];
+  int32_t version, precision, nx, ny, nz, theta_corr, hist;
+  int32_t has_Tw[2];
+  int64_t step;
+  double mass0, kappa_w;
+  uint64_t fbytes, gbytes, hbytes, twbytes;
+};
+constexpr char kSaveMagic[8] = {'L', 'B', 'M', '3', 'D', 'S', 'V', '1'};
+
+struct SaveSizes {
+  size_t f, g, h, tw, total;
+};
+
+SaveSizes save_sizes(const lbm_params& p) {
+  SaveSizes z;
+  const size_t NP = (size_t)p.nz * plane_pitch(p.nx, p.ny);
+  const size_t es = elem_size(p.precision), cs = compute_size(p.precision);
+  z.f = 19 * NP * es;
+  z.g = 7 * NP * es;
+  z.h = p.theta_corr ? (size_t)ncells(p) * cs : 0;
+  z.tw = (size_t)p.nx * p.ny * 8;
+  z.total = sizeof(SaveHeader) + z.f + z.g + 2 * z.h + 2 * z.tw;
+  return z;
+}
+
 }  // namespace
 
 extern "C" {
@@ -721,6 +753,77 @@ lbm_status lbm_set_kappa(lbm_ctx* ctx, double kappa_w) {
   if (!ctx) return LBM_EINVAL;
   if (!std::isfinite(kappa_w)) { ctx->err = "kappa_w must be finite"; return LBM_EINVAL; }
   ctx->p.kappa_w = kappa_w;
+  return LBM_OK;
+}
+
+lbm_status lbm_save_bytes(const lbm_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return LBM_EINVAL;
+  *bytes = save_sizes(ctx->p).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_save(lbm_ctx* ctx, void* host_dst, size_t bytes) {
+  if (!ctx || !host_dst) return LBM_EINVAL;
+  if (!ctx->initialised) { ctx->err = "lbm_save before lbm_init"; return LBM_ESTATE; }
+  const SaveSizes z = save_sizes(ctx->p);
+  if (bytes < z.total) { ctx->err = "lbm_save: buffer smaller than lbm_save_bytes"; return LBM_EINVAL; }
+  SaveHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kSaveMagic, 8);
+  h.version = 1;
+  h.precision = ctx->p.precision;
+  h.nx = ctx->p.nx; h.ny = ctx->p.ny; h.nz = ctx->p.nz;
+  h.theta_corr = ctx->p.theta_corr;
+  h.hist = ctx->hist;
+  h.has_Tw[0] = ctx->has_Tw[0]; h.has_Tw[1] = ctx->has_Tw[1];
+  h.step = ctx->step;
+  h.mass0 = ctx->mass0;
+  h.kappa_w = ctx->p.kappa_w;
+  h.fbytes = z.f; h.gbytes = z.g; h.hbytes = z.h; h.twbytes = z.tw;
+  char* o = (char*)host_dst;
+  std::memcpy(o, &h, sizeof(h));
+  o += sizeof(h);
+  const hipStream_t st = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(o, ctx->fA, z.f, hipMemcpyDeviceToHost, st)); o += z.f;
+  HIPCHK(ctx, hipMemcpyAsync(o, ctx->gA, z.g, hipMemcpyDeviceToHost, st)); o += z.g;
+  for (int k = 0; k < 2 && z.h; ++k) { HIPCHK(ctx, hipMemcpyAsync(o, ctx->Th[k], z.h, hipMemcpyDeviceToHost, st)); o += z.h; }
+  for (int k = 0; k < 2; ++k) { HIPCHK(ctx, hipMemcpyAsync(o, ctx->Tw[k], z.tw, hipMemcpyDeviceToHost, st)); o += z.tw; }
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx* ctx, const void* host_src, size_t bytes) {
+  if (!ctx || !host_src) return LBM_EINVAL;
+  const SaveSizes z = save_sizes(ctx->p);
+  SaveHeader h;
+  if (bytes < sizeof(h)) { ctx->err = "lbm_load: image too short"; return LBM_EINVAL; }
+  std::memcpy(&h, host_src, sizeof(h));
+  if (std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != 1) {
+    ctx->err = "lbm_load: not an image written by lbm_save"; return LBM_EINVAL;
+  }
+  if (h.precision != ctx->p.precision || h.nx != ctx->p.nx || h.ny != ctx->p.ny || h.nz != ctx->p.nz ||
+      h.theta_corr != ctx->p.theta_corr) {
+    ctx->err = "lbm_load: grid, precision or theta_corr differ from this context"; return LBM_EINVAL;
+  }
+  if (h.fbytes != z.f || h.gbytes != z.g || h.hbytes != z.h || h.twbytes != z.tw || bytes < z.total) {
+    ctx->err = "lbm_load: image size does not match this context"; return LBM_EINVAL;
+  }
+  if (h.hist < 0 || h.hist > 2) { ctx->err = "lbm_load: corrupt history count"; return LBM_EINVAL; }
+  const char* o = (const char*)host_src + sizeof(h);
+  const hipStream_t st = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->fA, o, z.f, hipMemcpyHostToDevice, st)); o += z.f;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->gA, o, z.g, hipMemcpyHostToDevice, st)); o += z.g;
+  for (int k = 0; k < 2 && z.h; ++k) { HIPCHK(ctx, hipMemcpyAsync(ctx->Th[k], o, z.h, hipMemcpyHostToDevice, st)); o += z.h; }
+  for (int k = 0; k < 2; ++k) { HIPCHK(ctx, hipMemcpyAsync(ctx->Tw[k], o, z.tw, hipMemcpyHostToDevice, st)); o += z.tw; }
+  HIPCHK(ctx, hipMemsetAsync(ctx->flag, 0, 64, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  ctx->step = h.step;
+  ctx->mass0 = h.mass0;
+  ctx->hist = h.hist;
+  ctx->has_Tw[0] = h.has_Tw[0] != 0;
+  ctx->has_Tw[1] = h.has_Tw[1] != 0;
+  ctx->p.kappa_w = h.kappa_w;
+  ctx->initialised = true;
   return LBM_OK;
 }
 

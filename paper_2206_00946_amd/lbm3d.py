@@ -56,8 +56,8 @@ class LbmAdjointSpec(ctypes.Structure):
 
 
 EXPORTS = ["lbm_default_params", "lbm_required_bytes", "lbm_create", "lbm_init", "lbm_set_wall_T",
-           "lbm_set_kappa", "lbm_step", "lbm_fields", "lbm_populations", "lbm_reduce", "lbm_adjoint_bytes",
-           "lbm_adjoint", "lbm_last_error", "lbm_destroy"]
+           "lbm_set_kappa", "lbm_step", "lbm_fields", "lbm_populations", "lbm_save_bytes", "lbm_save",
+           "lbm_load", "lbm_reduce", "lbm_adjoint_bytes", "lbm_adjoint", "lbm_last_error", "lbm_destroy"]
 
 _lib = None
 
@@ -86,6 +86,9 @@ def load_library():
     lib.lbm_fields.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     lib.lbm_populations.argtypes = [ctypes.c_void_p, dp, dp]
     lib.lbm_reduce.argtypes = [ctypes.c_void_p, P(LbmDiag)]
+    lib.lbm_save_bytes.argtypes = [ctypes.c_void_p, P(ctypes.c_size_t)]
+    lib.lbm_save.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+    lib.lbm_load.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     lib.lbm_adjoint_bytes.argtypes = [ctypes.c_void_p, P(LbmAdjointSpec), P(ctypes.c_size_t)]
     lib.lbm_adjoint.argtypes = [ctypes.c_void_p, P(LbmAdjointSpec), dp, ctypes.c_void_p, dp, ctypes.c_int32]
     lib.lbm_last_error.argtypes = [ctypes.c_void_p]
@@ -242,6 +245,19 @@ class Lbm3D:
         g = np.empty(7 * self.n)
         self._check(self.lib.lbm_populations(self.ctx, _dptr(f), _dptr(g)), self.ctx)
         return f.reshape((19,) + self.shape), g.reshape((7,) + self.shape)
+
+    def save(self) -> np.ndarray:
+        """Host image of the whole state (lbm_save), as a uint8 array."""
+        n = ctypes.c_size_t()
+        self._check(self.lib.lbm_save_bytes(self.ctx, ctypes.byref(n)), self.ctx)
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self.lib.lbm_save(self.ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes), self.ctx)
+        return buf
+
+    def load(self, image: np.ndarray) -> None:
+        """Resume from an image written by save() (lbm_load)."""
+        image = np.ascontiguousarray(image, dtype=np.uint8)
+        self._check(self.lib.lbm_load(self.ctx, image.ctypes.data_as(ctypes.c_void_p), image.nbytes), self.ctx)
 
     def reduce(self) -> Dict[str, float]:
         d = LbmDiag()
