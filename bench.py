@@ -65,12 +65,40 @@ FUSED_SOURCES = ["paper_2206_00946_amd/csrc/kernels_fused.h", "paper_2206_00946_
                  "include/lbm3d.h", "paper_2206_00946_amd/build.py"]
 
 
+def code_tokens(text: str) -> str:
+    """C/C++ source with comments removed and whitespace runs folded, so that
+    edits of comments alone leave the hash of the kernel sources as it was."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":                                  # string or character literal, kept whole
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):                  # C++ line comment
+            while i < n and text[i] != "\n":
+                i += 1
+        elif text.startswith("/*", i):                  # C block comment
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def fused_kernel_hash():
     h = hashlib.sha256()
     for rel in FUSED_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(rel.encode())
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            text = fh.read()
+        if not rel.endswith(".py"):
+            text = code_tokens(text)
+        h.update(rel.encode())
+        h.update(text.encode())
     return h.hexdigest()[:16]
 
 
