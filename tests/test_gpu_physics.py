@@ -139,10 +139,8 @@ def test_d2_law_with_and_without_correction(P):
     assert r1 > 0.99 and abs(K1 / K0 - 1) < 0.05
 
 
-def test_d2_law(P):
-    w = synth.named("droplet_open_128")
-    _log("d^2 law: droplet_open_128 FP32, 20000 steps, volume every 100")
-    sim = P.from_workload(w, "fp32")
+def _d2_series(P, w, prec):
+    sim = P.from_workload(w, prec)
     t, vol = [], []
     for k in range(201):
         d = sim.reduce()
@@ -150,15 +148,44 @@ def test_d2_law(P):
         vol.append(d["vol_smooth"])
         if k < 200:
             sim.step(100)
+    rho, _, T = sim.fields()
     sim.close()
     t, vol = np.array(t, dtype=float), np.array(vol)
-    D2 = (6.0 * vol / np.pi) ** (2.0 / 3.0)
-    sel = t >= 4000
-    A = np.vstack([t[sel], np.ones(sel.sum())]).T
-    (m, c), *_ = np.linalg.lstsq(A, D2[sel], rcond=None)
-    r2 = 1.0 - np.sum((D2[sel] - (m * t[sel] + c)) ** 2) / np.sum((D2[sel] - D2[sel].mean()) ** 2)
-    _log(f"  D0^2 {D2[0]:.1f}, K = {-m:.5e} per step, r^2 {r2:.5f}, final (D/D0)^2 {D2[-1] / D2[0]:.4f}")
-    assert m < 0 and r2 > 0.99
+    return t, (6.0 * vol / np.pi) ** (2.0 / 3.0), rho, T
+
+
+def test_d2_law(P):
+    """The 128^3 evaporating droplet (Zou-He outlets on all six faces, faces
+    at 1.1 T_sat) in FP64 and in FP32 deviation storage: (D/D0)^2 is linear
+    in t after the initial transient in both, and FP32 follows FP64."""
+    w = synth.named("droplet_open_128")
+    out = {}
+    for prec in ("fp64", "fp32"):
+        _log(f"d^2 law: droplet_open_128 {prec}, 20000 steps, volume every 100")
+        t, D2, rho, T = _d2_series(P, w, prec)
+        sel = t >= 4000
+        A = np.vstack([t[sel], np.ones(sel.sum())]).T
+        (m, c), *_ = np.linalg.lstsq(A, D2[sel], rcond=None)
+        r2 = 1.0 - np.sum((D2[sel] - (m * t[sel] + c)) ** 2) / np.sum((D2[sel] - D2[sel].mean()) ** 2)
+        _log(f"  {prec}: D0^2 {D2[0]:.1f}, K = {-m:.5e} per step, r^2 {r2:.5f}, "
+             f"final (D/D0)^2 {D2[-1] / D2[0]:.4f}")
+        assert m < 0 and r2 > 0.99
+        out[prec] = (D2 / D2[0], rho, T, -m)
+    d_curve = float(np.max(np.abs(out["fp32"][0] - out["fp64"][0])))
+    rel_rho = np.abs(out["fp32"][1] - out["fp64"][1]) / out["fp64"][1]
+    e_rho = float(rel_rho.max())
+    at = np.unravel_index(int(np.argmax(rel_rho)), rel_rho.shape)
+    c = np.array(rel_rho.shape) // 2
+    _log(f"  largest rho difference at (z, y, x) = {tuple(int(v) for v in at)}, "
+         f"{float(np.linalg.norm(np.array(at) - c)):.1f} cells from the centre, rho64 {float(out['fp64'][1][at]):.4f}; "
+         f"99.9th percentile {float(np.quantile(rel_rho, 0.999)):.2e}, median {float(np.median(rel_rho)):.2e}")
+    e_T = float(np.max(np.abs(out["fp32"][2] - out["fp64"][2]) / out["fp64"][2]))
+    e_K = abs(out["fp32"][3] / out["fp64"][3] - 1)
+    _log(f"  FP32 vs FP64 after 20000 steps: rho {e_rho:.2e}, T {e_T:.2e} (max relative), "
+         f"(D/D0)^2 curve {d_curve:.2e} (max absolute), K {e_K:.2e} (relative)")
+    # integral measures and T to 1e-4 / 1e-3; pointwise rho after 20000 steps
+    # to 1e-2 (the largest differences sit in the interface, see the log)
+    assert e_T < 1e-4 and d_curve < 1e-4 and e_K < 1e-3 and e_rho < 1e-2
 
 
 def test_saturated_heat_transfer_slope_ratio(P):
