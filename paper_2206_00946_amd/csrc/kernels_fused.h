@@ -639,6 +639,10 @@ inline bool fused_supported(const lbm_params& p) {
   const int ty = fused_tile_height(p.precision);
   if (p.nx % FTX != 0 || p.ny % ty != 0) return false;
   if (p.nz < 4) return false;
+  // buffer offsets are 32-bit: the 19 direction planes of one level must span
+  // less than the offset that marks a halo lane without a cell (0xFFFFFF00)
+  const long long es = p.precision == LBM_FP64 ? 8 : (p.precision == LBM_FP32_DEV ? 4 : 2);
+  if (19 * plane_pitch(p.nx, p.ny) * es >= 0xF0000000ll) return false;
   return true;
 }
 

@@ -1,0 +1,36 @@
+// Host check of which set-ups the single-pass kernel takes (no GPU needed):
+// prints "<name> <0|1>" per case.
+#include <cstdio>
+#include <cstring>
+
+#include "kernels_fused.h"
+
+static lbm_params box(int nx, int ny, int nz, int precision, int zkind) {
+  lbm_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.nx = nx; p.ny = ny; p.nz = nz;
+  p.precision = (lbm_precision)precision;
+  for (int k = 0; k < 6; ++k) p.face[k] = LBM_FACE_PERIODIC;
+  p.face[4] = p.face[5] = (lbm_face_kind)zkind;
+  return p;
+}
+
+int main() {
+  struct Case { const char* name; lbm_params p; };
+  lbm_params outlet = box(512, 512, 384, LBM_FP32_DEV, LBM_FACE_WALL);
+  outlet.face[5] = LBM_FACE_PRESSURE;
+  const Case cases[] = {
+      {"blobs_512x512x384_fp32", box(512, 512, 384, LBM_FP32_DEV, LBM_FACE_WALL)},
+      {"blobs_512x512x384_fp64", box(512, 512, 384, LBM_FP64, LBM_FACE_WALL)},
+      {"periodic_64x8x4_fp16", box(64, 8, 4, LBM_FP16_DEV, LBM_FACE_PERIODIC)},
+      {"ragged_96x8x8_fp32", box(96, 8, 8, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
+      {"short_64x8x3_fp32", box(64, 8, 3, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
+      {"outlet_512x512x384_fp32", outlet},
+      {"plane_4096x4096_fp64", box(4096, 4096, 8, LBM_FP64, LBM_FACE_WALL)},
+      {"plane_8192x4096_fp32", box(8192, 4096, 4, LBM_FP32_DEV, LBM_FACE_WALL)},
+      {"plane_8192x4096_fp64", box(8192, 4096, 4, LBM_FP64, LBM_FACE_WALL)},
+      {"plane_8192x8192_fp32", box(8192, 8192, 4, LBM_FP32_DEV, LBM_FACE_WALL)},
+  };
+  for (const Case& c : cases) std::printf("%s %d\n", c.name, lbm::fused_supported(c.p) ? 1 : 0);
+  return 0;
+}

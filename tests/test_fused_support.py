@@ -1,0 +1,37 @@
+"""Host check (no GPU) of the set-ups that take the single-pass kernel:
+x/y periodic, z periodic or walled, tile-divisible x/y, at least 4 planes,
+and direction planes small enough for the kernel's 32-bit buffer offsets
+(larger planes run the unfused kernels, which index with 64 bits)."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+EXPECTED = {
+    "blobs_512x512x384_fp32": 1, "blobs_512x512x384_fp64": 1, "periodic_64x8x4_fp16": 1,
+    "ragged_96x8x8_fp32": 0, "short_64x8x3_fp32": 0, "outlet_512x512x384_fp32": 0,
+    "plane_4096x4096_fp64": 1, "plane_8192x4096_fp32": 1, "plane_8192x4096_fp64": 0,
+    "plane_8192x8192_fp32": 0,
+}
+
+
+@pytest.fixture(scope="module")
+def results(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = tmp_path_factory.mktemp("fs") / "fused_support_check"
+    csrc = os.path.join(ROOT, "paper_2206_00946_amd", "csrc")
+    subprocess.run([HIPCC, "-x", "hip", "--offload-arch=gfx950", "-O1", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                    "-I", csrc, os.path.join(ROOT, "tests", "native", "fused_support_check.cpp"), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {line.split()[0]: int(line.split()[1]) for line in out.splitlines() if line.strip()}
+
+
+@pytest.mark.parametrize("name", sorted(EXPECTED))
+def test_fused_support(results, name):
+    assert results[name] == EXPECTED[name], results
