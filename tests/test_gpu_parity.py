@@ -313,6 +313,23 @@ def test_fused_matches_unfused_fp64(P, name, monkeypatch):
     _compare(f"{name} fused vs unfused", out[0], out[1], 1e-13, 1e-13, 1e-13)
 
 
+def test_fused_xcd_block_mapping_is_bitwise_the_same(P, monkeypatch):
+    """The optional tile-to-XCD mapping (LBM_FUSED_MAP=1: each XCD a 2 x 4
+    block of tiles, one chunk per column) changes only the schedule: every
+    tile computes its cells the same way, so the state is bitwise the same."""
+    w = synth.blobs_closed(nx=128, ny=32, nz=24, mean_blobs=3, rmin=4.0, rmax=6.0, seed=9)
+    out = []
+    for mapping in ("0", "1"):
+        monkeypatch.setenv("LBM_FUSED_MAP", mapping)
+        monkeypatch.setenv("LBM_FUSED_CHUNK", "24")
+        sim = P.from_workload(w, precision="fp32")
+        sim.step(12)
+        out.append(sim.fields())
+        sim.close()
+    for a, b, what in zip(out[0], out[1], ("rho", "u", "T")):
+        assert np.array_equal(a, b), what
+
+
 # ---------------------------------------------------------------- vartheta = 1
 
 def _theta1(w):
