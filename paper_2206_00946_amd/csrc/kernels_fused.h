@@ -622,6 +622,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
 // unit with room for the prefetch registers).  LBM_FUSED_TY=16 selects
 // 16-row tiles (fewer halo reads, 128-register limit) for 32- and 16-bit
 // storage; FP64 always uses 8 rows (its LDS rings need twice the space).
+// Read once, when a context is created.
 inline int fused_tile_height(int precision) {
   if (precision == LBM_FP64) return 8;
   if (const char* ev = std::getenv("LBM_FUSED_TY")) {
@@ -630,13 +631,13 @@ inline int fused_tile_height(int precision) {
   return 8;
 }
 
-inline bool fused_supported(const lbm_params& p) {
+inline bool fused_supported(const lbm_params& p, int ty) {
   for (int k = 0; k < 4; ++k)
     if (p.face[k] != LBM_FACE_PERIODIC) return false;
   const bool zper = p.face[4] == LBM_FACE_PERIODIC && p.face[5] == LBM_FACE_PERIODIC;
   const bool zwall = p.face[4] == LBM_FACE_WALL && p.face[5] == LBM_FACE_WALL;
   if (!zper && !zwall) return false;
-  const int ty = fused_tile_height(p.precision);
+  if (ty != 8 && (ty != 16 || p.precision == LBM_FP64)) return false;
   if (p.nx % FTX != 0 || p.ny % ty != 0) return false;
   if (p.nz < 4) return false;
   // buffer offsets are 32-bit: the 19 direction planes of one level must span
@@ -649,8 +650,11 @@ inline bool fused_supported(const lbm_params& p) {
 template <typename S>
 struct FusedImpl {
   using C = typename Storage<S>::C;
+  // ty: tile height (8, or 16 for 32/16-bit storage); chunk_planes: z planes
+  // per workgroup (0: all); xcd_map: give each XCD a 2 x 4 block of tiles
   static hipError_t step(const lbm_params& p, const Phys<C>& ph, hipStream_t stream, const S* fA, const S* gA, S* fB,
-                         S* gB, const double* Tw0, const double* Tw1, int* flag, int chunk_planes) {
+                         S* gB, const double* Tw0, const double* Tw1, int* flag, int ty, int chunk_planes,
+                         bool xcd_map) {
     FusedArgs<C> a;
     a.ph = ph;
     a.nx = p.nx;
@@ -659,15 +663,12 @@ struct FusedImpl {
     a.N = (long long)p.nx * p.ny * p.nz;
     a.pitch = plane_pitch(p.nx, p.ny);
     a.zwall = p.face[4] == LBM_FACE_WALL;
-    const int TY = fused_tile_height(p.precision);
+    const int TY = ty;
     a.tiles_x = p.nx / FTX;
     a.ntiles = a.tiles_x * (p.ny / TY);
     a.chunk = chunk_planes > 0 ? chunk_planes : p.nz;
     const int nchunks = (p.nz + a.chunk - 1) / a.chunk;
-    a.xcd_blocks = 0;
-    if (const char* ev = std::getenv("LBM_FUSED_MAP"))
-      a.xcd_blocks = std::atoi(ev) == 1 && nchunks == 1 && a.tiles_x % 2 == 0 && (p.ny / TY) % 4 == 0 &&
-                     a.ntiles % 8 == 0;
+    a.xcd_blocks = xcd_map && nchunks == 1 && a.tiles_x % 2 == 0 && (p.ny / TY) % 4 == 0 && a.ntiles % 8 == 0;
     a.wall_T[0] = (C)p.face_T[4];
     a.wall_T[1] = (C)p.face_T[5];
     a.wall_Tw[0] = Tw0;

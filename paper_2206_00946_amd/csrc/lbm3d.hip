@@ -69,6 +69,8 @@ struct lbm_ctx {
   double mass0 = 0.0;
   bool fused_ok = false;
   int fused_chunk = 0;  // z planes per workgroup of the fused kernel (0: all)
+  int fused_ty = 8;     // tile height of the fused kernel
+  bool fused_map = false;  // fused kernel: each XCD a 2 x 4 block of tiles
   std::string err;
 };
 
@@ -291,7 +293,8 @@ struct Impl {
   static hipError_t step_fused(lbm_ctx* ctx, const S* fs, const S* gs, S* fd, S* gd) {
     const lbm_params& p = ctx->p;
     return FusedImpl<S>::step(p, phys_of<C>(p), ctx->stream, fs, gs, fd, gd, ctx->has_Tw[0] ? ctx->Tw[0] : nullptr,
-                              ctx->has_Tw[1] ? ctx->Tw[1] : nullptr, ctx->flag, ctx->fused_chunk);
+                              ctx->has_Tw[1] ? ctx->Tw[1] : nullptr, ctx->flag, ctx->fused_ty, ctx->fused_chunk,
+                              ctx->fused_map);
   }
 
   static hipError_t step_from(lbm_ctx* ctx, S* fs, S* gs, S* fd, S* gd) {
@@ -678,10 +681,12 @@ lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_by
   ctx->sums = (double*)(b + L.off_sums);
   ctx->flag = (int*)(b + L.off_flag);
   ctx->staging = (double*)(b + L.off_stage);
-  ctx->fused_ok = fused_supported(*p) && p->theta_corr == 0;
+  ctx->fused_ty = fused_tile_height(p->precision);
+  ctx->fused_ok = fused_supported(*p, ctx->fused_ty) && p->theta_corr == 0;
+  if (const char* ev = std::getenv("LBM_FUSED_MAP")) ctx->fused_map = std::atoi(ev) == 1;
   {
     // enough workgroups to cover the 256 compute units twice, z chunks of >= 8 planes
-    const long long ntiles = (long long)(p->nx / FTX) * (p->ny / fused_tile_height(p->precision));
+    const long long ntiles = (long long)(p->nx / FTX) * (p->ny / ctx->fused_ty);
     long long nchunks = ntiles > 0 ? (512 + ntiles - 1) / ntiles : 1;
     nchunks = std::max(1ll, std::min(nchunks, (long long)p->nz / 8));
     ctx->fused_chunk = (int)((p->nz + nchunks - 1) / nchunks);

@@ -31,6 +31,10 @@ int main() {
       {"plane_8192x4096_fp64", box(8192, 4096, 4, LBM_FP64, LBM_FACE_WALL)},
       {"plane_8192x8192_fp32", box(8192, 8192, 4, LBM_FP32_DEV, LBM_FACE_WALL)},
   };
-  for (const Case& c : cases) std::printf("%s %d\n", c.name, lbm::fused_supported(c.p) ? 1 : 0);
+  for (const Case& c : cases) std::printf("%s %d\n", c.name, lbm::fused_supported(c.p, 8) ? 1 : 0);
+  // 16-row tiles: 32/16-bit storage only, ny a multiple of 16
+  std::printf("ty16_512x512x384_fp32 %d\n", lbm::fused_supported(box(512, 512, 384, LBM_FP32_DEV, LBM_FACE_WALL), 16));
+  std::printf("ty16_512x512x384_fp64 %d\n", lbm::fused_supported(box(512, 512, 384, LBM_FP64, LBM_FACE_WALL), 16));
+  std::printf("ty16_64x8x8_fp32 %d\n", lbm::fused_supported(box(64, 8, 8, LBM_FP32_DEV, LBM_FACE_PERIODIC), 16));
   return 0;
 }

@@ -16,6 +16,7 @@ EXPECTED = {
     "ragged_96x8x8_fp32": 0, "short_64x8x3_fp32": 0, "outlet_512x512x384_fp32": 0,
     "plane_4096x4096_fp64": 1, "plane_8192x4096_fp32": 1, "plane_8192x4096_fp64": 0,
     "plane_8192x8192_fp32": 0,
+    "ty16_512x512x384_fp32": 1, "ty16_512x512x384_fp64": 0, "ty16_64x8x8_fp32": 0,
 }
 
 
