@@ -167,7 +167,8 @@ lbm_status lbm_fields(lbm_ctx* ctx, double* rho, double* u, double* T, int32_t d
  * Host pointers; either may be NULL.  Synchronous. */
 lbm_status lbm_populations(lbm_ctx* ctx, double* f, double* g);
 
-/* Checkpoint and resume.  lbm_save writes the whole state of the context
+/* Checkpoint and resume (infrastructure around the method; the paper
+ * defines no such operation).  lbm_save writes the whole state of the context
  * into host memory: the current populations in their device layout and
  * storage format, the step counter, the initial mass (for evap_mass), the
  * wall temperature planes set by lbm_set_wall_T, kappa_w and, with
