@@ -288,7 +288,10 @@ def main():
                    "storage": args.precision, "faces": w["faces"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(head["frac"], 4), "traffic": traffic,
-                     "alg_bytes_per_cell": ALG_BYTES[args.precision]},
+                     "alg_bytes_per_cell": ALG_BYTES[args.precision],
+                     # the committed counters' bytes moved per launch at this run's step time
+                     "achieved_on_traffic": (round(traffic / (head["ms_per_step"] * 1e-3) / 1e9, 1)
+                                             if traffic else None)},
         "variants": variants,
         "accuracy": accuracy,
         "adjoint": adjoint,
