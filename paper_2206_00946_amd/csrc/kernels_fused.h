@@ -315,7 +315,12 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     if constexpr (PF) {
       int zn;
       if (ST) {
+        // memory instructions of the steady march are issued at wave
+        // priority 1, so that they reach the memory path ahead of arithmetic
+        // of the other wave on the SIMD
+        __builtin_amdgcn_s_setprio(1);
         load_f(p + 1, colb, pfi);
+        __builtin_amdgcn_s_setprio(0);
         next_loaded = true;
       } else if (p < p_end && plane_of(p + 1, zn)) {
         prefetch(zn);
@@ -394,7 +399,11 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     }
     __syncthreads();
     // ---------------------------------------------------------------- plane p-1: force, u, D3Q19
-    if constexpr (ST && PF) load_cell(p + 1, hcolb_pf, pfh);
+    if constexpr (ST && PF) {
+      __builtin_amdgcn_s_setprio(1);
+      load_cell(p + 1, hcolb_pf, pfh);
+      __builtin_amdgcn_s_setprio(0);
+    }
     finish_pulls();
     const int q = p - 1;
     int zq;
@@ -464,9 +473,11 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
             // steady march: the first kEarlyF directions here, the rest after
             // the next barrier, so that the plane's stores reach memory in two
             // smaller bursts
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int i = 0; i < kEarlyF; ++i)
               st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+            __builtin_amdgcn_s_setprio(0);
           } else if (!(a.zwall && (lo_out || hi_out))) {
 #pragma unroll
             for (int i = 0; i < 19; ++i)
@@ -499,6 +510,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       }
     }
     __syncthreads();
+    if constexpr (ST) __builtin_amdgcn_s_setprio(1);
     if constexpr (ST && PF) load_g(p + 1, colb, pfi);
     if constexpr (ST) {
       // the remaining D3Q19 pushes of plane q = p-1 (interior planes: no wrap)
@@ -508,6 +520,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
 #pragma unroll
       for (int i = kEarlyF; i < 19; ++i)
         st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+      __builtin_amdgcn_s_setprio(0);
     }
     // ---------------------------------------------------------------- divergence contributions of u(q)
     if (do_u) {
