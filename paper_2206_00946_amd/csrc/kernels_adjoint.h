@@ -34,6 +34,41 @@ __device__ __forceinline__ bool z_inside(const Geom& g, int& z) {
   return false;
 }
 
+// Neighbour addressing of cell (x, y, z) with x and y periodic: in-plane
+// offsets of x +- 1 and y +- 1 with wrap, and the levels z - 1, z, z + 1
+// (wrapped when z is periodic; zin false beyond a bounded face).  Replaces
+// the per-neighbour 64-bit index arithmetic of cell_index / pidx.
+struct AdjNbr {
+  int col;
+  int ox[3], oy[3];
+  int zl[3];
+  bool zin[3];
+  long long PS, pitch;
+  __device__ __forceinline__ AdjNbr(const Geom& g, int x, int y, int z) {
+    col = x + g.nx * y;
+    ox[0] = x == 0 ? g.nx - 1 : -1;
+    ox[1] = 0;
+    ox[2] = x == g.nx - 1 ? 1 - g.nx : 1;
+    oy[0] = y == 0 ? (g.ny - 1) * g.nx : -g.nx;
+    oy[1] = 0;
+    oy[2] = y == g.ny - 1 ? (1 - g.ny) * g.nx : g.nx;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      zl[d] = z + d - 1;
+      zin[d] = z_inside(g, zl[d]);
+    }
+    PS = (long long)g.nx * g.ny;
+    pitch = g.pitch;
+  }
+  // column of x + s c_i (s = +1 or -1)
+  __device__ __forceinline__ int ncol(int i, int s) const { return col + ox[s * CX[i] + 1] + oy[s * CY[i] + 1]; }
+  // cell index and population index at column cl, level zz
+  __device__ __forceinline__ long long cell(int zz, int cl) const { return (long long)zz * PS + cl; }
+  __device__ __forceinline__ long long pop(int Q, int i, int zz, int cl) const {
+    return ((long long)zz * Q + i) * pitch + cl;
+  }
+};
+
 template <typename C>
 __device__ __forceinline__ C varpi(int i) {
   return i < 7 ? C(1) / C(6) : C(1) / C(12);
@@ -82,28 +117,32 @@ __global__ void __launch_bounds__(256)
   const C rho = rho_f[c], T = T_f[c];
   const C ux = ueq[c], uy = ueq[c + N], uz = ueq[c + 2 * N];
   const C dux = du[c], duy = du[c + N], duz = du[c + 2 * N];
+  const AdjNbr nb(g, x, y, z);
+  const int col = nb.col;
+  auto ncol = [&](int i) { return nb.ncol(i, 1); };
+  auto pop = [&](int Q, int i, int zz, int cl) { return nb.pop(Q, i, zz, cl); };
+  const bool* zin = nb.zin;
+  const int* zl = nb.zl;
 
   // S9: f*_i(x) went to slot i at x + c_i, to slot opp(i) at x (wall), or
   // left the domain (outlet)
   C fsb[19];
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const int xd = wrapp(x + CX[i], g.nx), yd = wrapp(y + CY[i], g.ny);
-    int zd = z + CZ[i];
-    if (z_inside(g, zd)) fsb[i] = lfi[pidx(g, 19, i, xd, yd, zd)];
-    else if (g.face[zd < 0 ? 4 : 5] == FACE_WALL) fsb[i] = lfi[pidx(g, 19, opp19(i), x, y, z)];
+    const int d = CZ[i] + 1;
+    if (zin[d]) fsb[i] = lfi[pop(19, i, zl[d], ncol(i))];
+    else if (g.face[CZ[i] < 0 ? 4 : 5] == FACE_WALL) fsb[i] = lfi[pop(19, opp19(i), z, col)];
     else fsb[i] = C(0);
   }
   // S10: g*_i(x) enters the blend at y = x + c_i with weight 1/(rho(y) c_v)
   C gsb[7];
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
-    const int xd = wrapp(x + CX[i], g.nx), yd = wrapp(y + CY[i], g.ny);
-    int zd = z + CZ[i];
+    const int d = CZ[i] + 1;
     gsb[i] = C(0);
-    if (z_inside(g, zd)) {
-      const long long cd = cell_index(g, xd, yd, zd);
-      gsb[i] = lgi[pidx(g, 7, i, xd, yd, zd)] / (rho_f[cd] * ph.cv);
+    if (zin[d]) {
+      const long long cd = nb.cell(zl[d], ncol(i));
+      gsb[i] = lgi[pop(7, i, zl[d], ncol(i))] / (rho_f[cd] * ph.cv);
     }
   }
   C fb[19], gb[7];
@@ -116,7 +155,7 @@ __global__ void __launch_bounds__(256)
   // S6 (local part): Fbar = rho c_v u . grad T + T (dp/dT) div u
   C gp[7];
 #pragma unroll
-  for (int i = 0; i < 7; ++i) gp[i] = Storage<S>::load(gA + pidx(g, 7, i, x, y, z));
+  for (int i = 0; i < 7; ++i) gp[i] = Storage<S>::load(gA + pop(7, i, z, col));
   C gx, gy, gz;
   local_gradT(gp, ph.vflux, ph, gx, gy, gz);
   const C rux = ux + C(0.5) * dux, ruy = uy + C(0.5) * duy, ruz = uz + C(0.5) * duz;
@@ -125,13 +164,11 @@ __global__ void __launch_bounds__(256)
   C div = C(0);
 #pragma unroll
   for (int i = 1; i < 19; ++i) {
-    const int xn = wrapp(x + CX[i], g.nx), yn = wrapp(y + CY[i], g.ny);
-    int zn = z + CZ[i];
+    const int d = CZ[i] + 1;
     C v = C(0);
-    if (z_inside(g, zn) || g.face[zn < 0 ? 4 : 5] == FACE_PRESSURE) {
-      if (zn < 0) zn = 0;
-      if (zn >= g.nz) zn = g.nz - 1;
-      const long long cn = cell_index(g, xn, yn, zn);
+    if (zin[d] || g.face[CZ[i] < 0 ? 4 : 5] == FACE_PRESSURE) {
+      const int zn = zin[d] ? zl[d] : z;   // beyond an outlet: the face node's own level
+      const long long cn = nb.cell(zn, ncol(i));
       if (CX[i]) v += C(CX[i]) * ureal[cn];
       if (CY[i]) v += C(CY[i]) * ureal[cn + N];
       if (CZ[i]) v += C(CZ[i]) * ureal[cn + 2 * N];
@@ -157,14 +194,13 @@ __global__ void __launch_bounds__(256)
   const C inv = C(1) / (rho * ph.cv);
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
-    const C l = lgi[pidx(g, 7, i, x, y, z)];
-    int zs = z - CZ[i];
-    if (z_inside(g, zs)) {
+    const C l = lgi[pop(7, i, z, col)];
+    if (zin[1 - CZ[i]]) {
       gb[i] += l * (C(1) - inv);
       if (n.count == 0) {
         // the adjoint of s_{t+1} vanishes on bounded-face nodes, where the
         // next step's Dirichlet condition overwrites g
-        const C gn = Storage<S>::load(gnext + pidx(g, 7, i, x, y, z));
+        const C gn = Storage<S>::load(gnext + pop(7, i, z, col));
         rb -= l * (gn - gp[i]) / rho;
       }
     } else {
@@ -186,9 +222,9 @@ __global__ void __launch_bounds__(256)
     }
   }
 #pragma unroll
-  for (int i = 0; i < 19; ++i) lfo[pidx(g, 19, i, x, y, z)] = fb[i];
+  for (int i = 0; i < 19; ++i) lfo[pop(19, i, z, col)] = fb[i];
 #pragma unroll
-  for (int i = 0; i < 7; ++i) lgo[pidx(g, 7, i, x, y, z)] = gb[i];
+  for (int i = 0; i < 7; ++i) lgo[pop(7, i, z, col)] = gb[i];
   a_rho[c] = rb;
   a_T[c] = Tb;
   a_div[c] = divb;
@@ -224,15 +260,14 @@ __global__ void __launch_bounds__(256)
   if (!n.wall) {
     // readers of u(y): x = y - c_i directly, and on an outlet plane the
     // same-plane readers whose ghost neighbour is a copy of y
+    const AdjNbr nb(g, x, y, z);
     C vb[3] = {C(0), C(0), C(0)};
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
-      const int xr = wrapp(x - CX[i], g.nx), yr = wrapp(y - CY[i], g.ny);
-      int zr = z - CZ[i];
+      const int cr = nb.ncol(i, -1);
       C d = C(0);
-      if (z_inside(g, zr)) d += a_div[cell_index(g, xr, yr, zr)];
-      const int zo = z + CZ[i];
-      if ((zo < 0 || zo >= g.nz) && g.face[zo < 0 ? 4 : 5] == FACE_PRESSURE) d += a_div[cell_index(g, xr, yr, z)];
+      if (nb.zin[1 - CZ[i]]) d += a_div[nb.cell(nb.zl[1 - CZ[i]], cr)];
+      if (!nb.zin[1 + CZ[i]] && g.face[CZ[i] < 0 ? 4 : 5] == FACE_PRESSURE) d += a_div[nb.cell(z, cr)];
       d *= C(3) * w19<C>(i);
       vb[0] += C(CX[i]) * d;
       vb[1] += C(CY[i]) * d;
@@ -244,15 +279,15 @@ __global__ void __launch_bounds__(256)
       dub[a] += C(0.5) * vb[a];
     }
   }
-  const C rho = rho_f[c];
+  const C irho = C(1) / rho_f[c];
   C rb = a_rho[c];
   C jb[3], Fb[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     // u_eq = j / rho (the wall value was moved to du in k_adj_collide), du = F / rho
-    jb[a] = ueb[a] / rho;
-    Fb[a] = dub[a] / rho;
-    rb -= (ueb[a] * ueq[c + a * N] + dub[a] * du[c + a * N]) / rho;
+    jb[a] = ueb[a] * irho;
+    Fb[a] = dub[a] * irho;
+    rb -= (ueb[a] * ueq[c + a * N] + dub[a] * du[c + a * N]) * irho;
   }
   if (n.pressure) {
     C fb[19];
@@ -330,27 +365,29 @@ __global__ void __launch_bounds__(256)
   const long long N = g.N;
   const long long P = (long long)g.nx * g.ny;
   const Node n = classify(g, x, y, z);
+  const AdjNbr nb(g, x, y, z);
   // F(y) = -G psi(y) sum_i varpi_i c_i psi(y + c_i)
   C acx = C(0), acy = C(0), acz = C(0);
   C pb = C(0);
 #pragma unroll
   for (int i = 1; i < 19; ++i) {
-    const C pn = psi_at(psi, g, ph.kappa_w, x + CX[i], y + CY[i], z + CZ[i]);
+    const int d = CZ[i] + 1;
+    // psi(y + c_i): a node, or the ghost beyond a bounded z face
+    const C pn = nb.zin[d] ? psi[nb.cell(nb.zl[d], nb.ncol(i, 1))]
+                           : psi_at(psi, g, ph.kappa_w, x + CX[i], y + CY[i], z + CZ[i]);
     acx += varpi<C>(i) * C(CX[i]) * pn;
     acy += varpi<C>(i) * C(CY[i]) * pn;
     acz += varpi<C>(i) * C(CZ[i]) * pn;
     // y as the neighbour x + c_i of the readers x = y - c_i, and of the
     // same-plane readers beyond an outlet (ghost = copy of y)
-    const int xr = wrapp(x - CX[i], g.nx), yr = wrapp(y - CY[i], g.ny);
-    int zr = z - CZ[i];
+    const int cl = nb.ncol(i, -1);
     const C wc = -ph.G * varpi<C>(i);
-    if (z_inside(g, zr)) {
-      const long long cr = cell_index(g, xr, yr, zr);
+    if (nb.zin[1 - CZ[i]]) {
+      const long long cr = nb.cell(nb.zl[1 - CZ[i]], cl);
       pb += wc * psi[cr] * (C(CX[i]) * Fb[cr] + C(CY[i]) * Fb[cr + N] + C(CZ[i]) * Fb[cr + 2 * N]);
     }
-    const int zo = z + CZ[i];
-    if ((zo < 0 || zo >= g.nz) && g.face[zo < 0 ? 4 : 5] == FACE_PRESSURE) {
-      const long long cr = cell_index(g, xr, yr, z);
+    if (!nb.zin[d] && g.face[CZ[i] < 0 ? 4 : 5] == FACE_PRESSURE) {
+      const long long cr = nb.cell(z, cl);
       pb += wc * psi[cr] * (C(CX[i]) * Fb[cr] + C(CY[i]) * Fb[cr + N] + C(CZ[i]) * Fb[cr + 2 * N]);
     }
   }
@@ -363,10 +400,10 @@ __global__ void __launch_bounds__(256)
     const int zw = s ? g.nz - 1 : 0;
     const int zi = s ? g.nz - 2 : 1;
     const long long o = s * P;
-    if (z == zi) pb += gadj[o + x + (long long)g.nx * y];
+    if (z == zi) pb += gadj[o + nb.col];
     if (z == zw) {
-      pb += ax[o + wrapp(x - 1, g.nx) + (long long)g.nx * y] - ax[o + wrapp(x + 1, g.nx) + (long long)g.nx * y] +
-            ay[o + x + (long long)g.nx * wrapp(y - 1, g.ny)] - ay[o + x + (long long)g.nx * wrapp(y + 1, g.ny)];
+      pb += ax[o + nb.col + nb.ox[0]] - ax[o + nb.col + nb.ox[2]] + ay[o + nb.col + nb.oy[0]] -
+            ay[o + nb.col + nb.oy[2]];
     }
   }
   // eq. (7): psi = sqrt(2 (p - rho/3) / G)
@@ -380,12 +417,12 @@ __global__ void __launch_bounds__(256)
     const C jx = jb_f[c], jy = jb_f[c + N], jz = jb_f[c + 2 * N];
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-      const long long k = pidx(g, 19, i, x, y, z);
+      const long long k = nb.pop(19, i, z, nb.col);
       lfo[k] += rb + C(CX[i]) * jx + C(CY[i]) * jy + C(CZ[i]) * jz;
     }
   }
 #pragma unroll
-  for (int i = 0; i < 7; ++i) lgo[pidx(g, 7, i, x, y, z)] += Tb;
+  for (int i = 0; i < 7; ++i) lgo[nb.pop(7, i, z, nb.col)] += Tb;
 }
 
 // Reverse of S0 on the z faces, one thread per (x, y): g_i(x_b) = w_i T_b +
