@@ -2,11 +2,13 @@
 // population once and writes it once (Huang, Wang, He & Huang, arXiv
 // 2206.00946, Sec. 2 and 3.1).
 //
-// Domain: periodic in x and y; z periodic or bounded by two no-slip walls
-// (ghost psi of eq. (37): the first interior layer plus kappa_w times the
-// tangential difference magnitude on the wall layer).  nx must be a multiple
-// of 64 and ny a multiple of the tile height.  Other set-ups use the
-// unfused kernels.
+// Domain: periodic in x and y; z periodic, or bounded by two faces each a
+// no-slip wall (ghost psi of eq. (37): the first interior layer plus kappa_w
+// times the tangential difference magnitude on the wall layer) or a
+// constant-pressure outlet (Sec. 3.3: rho = rho_out on the face, unknown
+// populations filled, ghost psi and u copies of the face node).  nx must be
+// a multiple of 64 and ny a multiple of the tile height.  Other set-ups use
+// the unfused kernels.
 //
 // A workgroup owns a 64 x TY column tile (one wavefront per row, one thread
 // per column) and marches through z.  For every plane p it loads the
@@ -22,9 +24,9 @@
 // one plane later (its own old value, the source's g* through LDS); transfers
 // leaving the tile use the halo's old values kept in a small LDS ring; z
 // transfers stay in the thread's column registers.
-// Dirichlet temperatures on wall nodes (eqs. (35)-(36)) are applied to the
-// values loaded for a wall plane, from the next plane inward; a time step is
-// exactly one launch of this kernel.
+// Dirichlet temperatures on bounded-face nodes (eqs. (35)-(36)) are applied
+// to the values loaded for a face plane, from the next plane inward; a time
+// step is exactly one launch of this kernel.
 #pragma once
 
 #include <cstdlib>
@@ -50,11 +52,13 @@ struct FusedArgs {
   int nx, ny, nz;
   long long N;
   long long pitch;  // elements from one direction plane to the next
-  int zwall;  // 1: no-slip walls at z = 0 and z = nz - 1; 0: periodic z
+  int zbound;      // 1: z bounded by the faces at z = 0 and z = nz - 1; 0: periodic z
+  int zpres[2];    // bounded face is a pressure outlet (1) or a no-slip wall (0)
+  C face_rho[2];   // rho_out of a pressure face
   int tiles_x, ntiles, chunk;
   int xcd_blocks;  // 1: each XCD owns a 2 x 4 block of the tile grid
-  C wall_T[2];            // Dirichlet temperatures of the z = 0 and z = nz - 1 walls
-  const double* wall_Tw[2];  // optional per-cell wall temperature fields (nx*ny)
+  C wall_T[2];            // Dirichlet temperatures of the z = 0 and z = nz - 1 faces
+  const double* wall_Tw[2];  // optional per-cell face temperature fields (nx*ny)
   int* flag;
 };
 
@@ -119,6 +123,37 @@ struct Tile {
 
 __device__ __forceinline__ int wrapn(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Node of a z pressure face (hi: the face at z = nz - 1, else z = 0), Sec.
+// 3.3.  After streaming the node knows the populations with c_z = 0 or c_z
+// pointing out of the domain; the outlet condition uses their combination
+// rho_ref + sum_{c_z = 0} f + 2 sum_{c_z outward} f (deviations).
+template <typename C>
+__device__ __forceinline__ C outlet_known(const C* f, int hi, C rho_ref) {
+  C s0 = C(0), s1 = C(0);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    if (CZ[i] == 0) s0 += f[i];
+    else if (CZ[i] == (hi ? 1 : -1)) s1 += f[i];
+  }
+  return s0 + C(2) * s1 + rho_ref;
+}
+// u_eq = j / rho_out at such a node from the known sum kn and the force F:
+// the filled populations carry the tangential momenta -F_x/2, -F_y/2 (the
+// real tangential velocity is zero) and the outward momentum
+// rho_out u_n - F_n/2 with u_n = (kn + F_n/2 - rho_out) / rho_out.  Equal to
+// filling the unknowns and summing c_i f_i, up to rounding, and the same on
+// whichever thread evaluates it.
+template <typename C>
+__device__ __forceinline__ void outlet_ueq(C kn, int hi, C rho_out, C Fx, C Fy, C Fz, C& ux, C& uy, C& uz) {
+  const C sn = hi ? C(1) : C(-1);
+  const C Fn = sn * Fz;
+  const C ir = rcp(rho_out);
+  const C un = (kn + C(0.5) * Fn - rho_out) * ir;
+  ux = (-C(0.5) * Fx) * ir;
+  uy = (-C(0.5) * Fy) * ir;
+  uz = sn * (rho_out * un - C(0.5) * Fn) * ir;
+}
+
 // Population access with the plane-major layout: one buffer descriptor over
 // all directions of one plane (uniform, scalar registers), the direction as a
 // scalar byte offset (i * plane bytes) and the cell as a per-lane byte offset.
@@ -133,7 +168,10 @@ __device__ __forceinline__ void st_at(S* plane, unsigned bytes, unsigned voff, u
   Buf<S>::template store<store_cache_policy<S>()>(buffer_range(plane, bytes), voff, soff, v);
 }
 
-template <typename S, int TY>
+// OUT: the set-up has a pressure z face.  Closed and periodic set-ups run
+// the instantiation without the outlet code, which keeps that code's scalar
+// registers out of the march.
+template <typename S, int TY, bool OUT>
 __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, const S* __restrict__ gA,
                                                    S* __restrict__ fB, S* __restrict__ gB,
                                                    FusedArgs<typename Storage<S>::C> a) {
@@ -211,7 +249,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   int pend_z = 0;
 
   auto plane_of = [&](int p, int& zp) -> bool {
-    if (a.zwall) {
+    if (a.zbound) {
       zp = p;
       return p >= 0 && p < nz;
     }
@@ -328,10 +366,11 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       }
     }
     if (exists) {
-      const bool wall_plane = !ST && a.zwall && (zp == 0 || zp == nz - 1);
+      const bool face_plane = !ST && a.zbound && (zp == 0 || zp == nz - 1);
       const int zin = zp == 0 ? 1 : nz - 2;
       const int wk = zp == 0 ? 0 : 1;
-      // eqs. (35)-(36) on a wall plane: g_b = w T_b + g(x_f) - w T(x_f), on deviations
+      const bool pres_plane = OUT && face_plane && a.zpres[wk];
+      // eqs. (35)-(36) on a face plane: g_b = w T_b + g(x_f) - w T(x_f), on deviations
       auto dirichlet = [&](C* g7, unsigned off, unsigned fcol) {
         const S* gin = gA + PS * 7 * zin;
         C gf[7], sfg = C(0);
@@ -345,7 +384,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
 #pragma unroll
         for (int i = 0; i < 7; ++i) g7[i] = gf[i] + (i == 0 ? ph.w0 : ph.w1) * d;
       };
-      if (wall_plane) dirichlet(gc, colb, col);
+      if (face_plane) dirichlet(gc, colb, col);
       C sf = C(0), jx = C(0), jy = C(0), jz = C(0), sg = C(0);
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
@@ -356,16 +395,24 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       }
 #pragma unroll
       for (int i = 0; i < 7; ++i) sg += gc[i];
-      rho_c = ph.rho_ref + sf;
+      // rho = rho_out on a pressure face; u_eq there needs the force, so the
+      // plane keeps the outlet sum of the known populations instead
+      rho_c = pres_plane ? a.face_rho[wk] : ph.rho_ref + sf;
       const C T = ph.T_ref + sg;
       const C rad = psi_radicand(rho_c, T, ph);
       if (nonphysical(rho_c, T, rad, ph)) a.flag[0] = 1;
       s_psi[s3][e_own] = fsqrt(rad);
       s_rho[s4][e_own] = rho_c;
-      const C ir = rcp(rho_c);
-      s_ueq[s2][0][e_own] = jx * ir;
-      s_ueq[s2][1][e_own] = jy * ir;
-      s_ueq[s2][2][e_own] = jz * ir;
+      if (pres_plane) {
+        s_ueq[s2][0][e_own] = C(0);
+        s_ueq[s2][1][e_own] = C(0);
+        s_ueq[s2][2][e_own] = outlet_known(fb, wk, ph.rho_ref);
+      } else {
+        const C ir = rcp(rho_c);
+        s_ueq[s2][0][e_own] = jx * ir;
+        s_ueq[s2][1][e_own] = jy * ir;
+        s_ueq[s2][2][e_own] = jz * ir;
+      }
       if (has_halo) {
         if constexpr (!PF) {
           C lh[26];
@@ -375,7 +422,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
 #pragma unroll
           for (int i = 0; i < 7; ++i) gv[i] = lh[19 + i];
         }
-        if (wall_plane) dirichlet(gv, hcolb, hcol);
+        if (face_plane) dirichlet(gv, hcolb, hcol);
         C hs = C(0), hx = C(0), hy = C(0), hz = C(0), hg = C(0);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
@@ -386,14 +433,20 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         }
 #pragma unroll
         for (int i = 0; i < 7; ++i) hg += gv[i];
-        const C hr = ph.rho_ref + hs;
+        const C hr = pres_plane ? a.face_rho[wk] : ph.rho_ref + hs;
         const C hT = ph.T_ref + hg;
         s_psi[s3][he] = fsqrt(psi_radicand(hr, hT, ph));
         s_rho[s4][he] = hr;
-        const C ihr = rcp(hr);
-        s_ueq[s2][0][he] = hx * ihr;
-        s_ueq[s2][1][he] = hy * ihr;
-        s_ueq[s2][2][he] = hz * ihr;
+        if (pres_plane) {
+          s_ueq[s2][0][he] = C(0);
+          s_ueq[s2][1][he] = C(0);
+          s_ueq[s2][2][he] = outlet_known(hv, wk, ph.rho_ref);
+        } else {
+          const C ihr = rcp(hr);
+          s_ueq[s2][0][he] = hx * ihr;
+          s_ueq[s2][1][he] = hy * ihr;
+          s_ueq[s2][2][he] = hz * ihr;
+        }
         if (ridx >= 0) s_gr[s4][ridx] = gv[rdir];
       }
     }
@@ -406,15 +459,22 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     }
     finish_pulls();
     const int q = p - 1;
-    int zq;
-    const bool do_u = ST ? (zq = q, true) : (q >= z0 - 1 && plane_of(q, zq));
+    int zq = q;
+    const bool do_u = ST ? true : (q >= z0 - 1 && plane_of(q, zq));
+    // plane q on a bounded face: wall or pressure; ghost_cz = the c_z whose
+    // neighbours lie beyond a pressure face (their u is a copy of plane q)
+    const bool face_q = !ST && do_u && a.zbound && (zq == 0 || zq == nz - 1);
+    const int qk = zq == 0 ? 0 : 1;
+    const bool pres_q = OUT && face_q && a.zpres[qk];
+    const int ghost_cz = pres_q ? (qk ? 1 : -1) : 0;
     if (do_u) {
       // psi slots of planes q-1, q, q+1 (walls: the ghost layer mirrors the
-      // first interior layer, eq. (37) with theta = 90 degrees)
+      // first interior layer, eq. (37) with theta = 90 degrees; pressure
+      // faces: it copies the face plane)
       int sm = (k + 1) % 3, s0 = (k + 2) % 3, sp = s3;
-      if (!ST && a.zwall && zq == 0) sm = sp;
-      if (!ST && a.zwall && zq == nz - 1) sp = sm;
-      const bool wall_plane = !ST && a.zwall && (zq == 0 || zq == nz - 1);
+      if (face_q && zq == 0) sm = pres_q ? s0 : sp;
+      if (face_q && zq == nz - 1) sp = pres_q ? s0 : sm;
+      const bool wall_plane = face_q && !pres_q;
       const int sq = (k + 1) & 1;  // ueq slot of plane q
       const int rq = (k + 3) & 3;  // rho slot of plane q
       // eq. (37): the ghost layer adds kappa_w |grad_t psi| of the wall layer
@@ -454,6 +514,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
           uex = -C(0.5) * dux;
           uey = -C(0.5) * duy;
           uez = -C(0.5) * duz;
+        } else if (pres_q) {
+          outlet_ueq(uez, qk, rho, Fx, Fy, Fz, uex, uey, uez);
         }
         ub[0] = uex + C(0.5) * dux;
         ub[1] = uey + C(0.5) * duy;
@@ -462,9 +524,15 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         s_u[1][e_own] = ub[1];
         s_u[2][e_own] = ub[2];
         if (ST || (q >= z0 && q < z1)) {
+          if (pres_q) {
+            // Sec. 3.3: the unknown populations of the outlet node
+            const C F3[3] = {Fx, Fy, Fz};
+            outlet_fill(fa, 4 + qk, rho, F3, ph);
+          }
           collide19(fa, rho, rho - ph.rho_ref, uex, uey, uez, dux, duy, duz, ph);
           // destination planes q-1, q, q+1 (periodic wrap); at a wall the
-          // links leaving the domain bounce back onto the opposite slot
+          // links leaving the domain bounce back onto the opposite slot, at
+          // a pressure face they leave
           const bool lo_out = !ST && zq == 0, hi_out = !ST && zq == nz - 1;
           S* pm = fB + PS * 19 * (lo_out ? nz - 1 : zq - 1);
           S* p0 = fB + PS * 19 * zq;
@@ -478,7 +546,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
             for (int i = 0; i < kEarlyF; ++i)
               st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
             __builtin_amdgcn_s_setprio(0);
-          } else if (!(a.zwall && (lo_out || hi_out))) {
+          } else if (!(a.zbound && (lo_out || hi_out))) {
 #pragma unroll
             for (int i = 0; i < 19; ++i)
               st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
@@ -486,8 +554,9 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
               const bool out = (CZ[i] < 0 && lo_out) || (CZ[i] > 0 && hi_out);
-              if (out) st_at(p0, F19, colb, opp19(i) * PB, fa[i]);
-              else st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+              if (out) {
+                if (!pres_q) st_at(p0, F19, colb, opp19(i) * PB, fa[i]);
+              } else st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
             }
           }
         }
@@ -499,10 +568,13 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         if (!wall_plane) {
           C Fx, Fy, Fz;
           force_at(re, Fx, Fy, Fz);
-          const C ir = rcp(s_rho[rq][re]);
-          vx = s_ueq[sq][0][re] + C(0.5) * (Fx * ir);
-          vy = s_ueq[sq][1][re] + C(0.5) * (Fy * ir);
-          vz = s_ueq[sq][2][re] + C(0.5) * (Fz * ir);
+          const C rr = s_rho[rq][re];
+          const C ir = rcp(rr);
+          C ex = s_ueq[sq][0][re], ey = s_ueq[sq][1][re], ez = s_ueq[sq][2][re];
+          if (pres_q) outlet_ueq(ez, qk, rr, Fx, Fy, Fz, ex, ey, ez);
+          vx = ex + C(0.5) * (Fx * ir);
+          vy = ey + C(0.5) * (Fy * ir);
+          vz = ez + C(0.5) * (Fz * ir);
         }
         s_u[0][re] = vx;
         s_u[1][re] = vy;
@@ -531,6 +603,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         if (CZ[i] > 0) d0 += c;        // u(q) is the +z neighbour of plane q-1 = p-2
         else if (CZ[i] == 0) d1 += c;  // in-plane neighbour of plane q
         else d2 += c;                  // -z neighbour of plane q+1 = p
+        // beyond a pressure face the ghost u copies plane q
+        if (!ST && CZ[i] != 0 && CZ[i] == ghost_cz) d1 += c;
       }
     }
     // ---------------------------------------------------------------- plane p-2: D3Q7
@@ -554,7 +628,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         int zd = zr + 1;
         bool ok = true;
         if (!ST && zd >= nz) {
-          if (a.zwall) ok = false; else zd = 0;
+          if (a.zbound) ok = false; else zd = 0;
         }
         if (ok)
           st_at(gB + PS * 7 * zd, G7, colb, 5 * PB, gb[5] + (ga[5] - gb[5]) * (inv_cv * rcp(rho_b)));
@@ -564,7 +638,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         int zd = zr - 1;
         bool ok = true;
         if (!ST && zd < 0) {
-          if (a.zwall) ok = false; else zd = nz - 1;
+          if (a.zbound) ok = false; else zd = nz - 1;
         }
         if (ok)
           st_at(gB + PS * 7 * zd, G7, colb, 6 * PB, g6_old + (ga[6] - g6_old) * (inv_cv * rcp(pend_rho)));
@@ -648,8 +722,8 @@ inline bool fused_supported(const lbm_params& p, int ty) {
   for (int k = 0; k < 4; ++k)
     if (p.face[k] != LBM_FACE_PERIODIC) return false;
   const bool zper = p.face[4] == LBM_FACE_PERIODIC && p.face[5] == LBM_FACE_PERIODIC;
-  const bool zwall = p.face[4] == LBM_FACE_WALL && p.face[5] == LBM_FACE_WALL;
-  if (!zper && !zwall) return false;
+  const bool zbound = p.face[4] != LBM_FACE_PERIODIC && p.face[5] != LBM_FACE_PERIODIC;
+  if (!zper && !zbound) return false;
   if (ty != 8 && (ty != 16 || p.precision == LBM_FP64)) return false;
   if (p.nx % FTX != 0 || p.ny % ty != 0) return false;
   if (p.nz < 4) return false;
@@ -675,7 +749,11 @@ struct FusedImpl {
     a.nz = p.nz;
     a.N = (long long)p.nx * p.ny * p.nz;
     a.pitch = plane_pitch(p.nx, p.ny);
-    a.zwall = p.face[4] == LBM_FACE_WALL;
+    a.zbound = p.face[4] != LBM_FACE_PERIODIC;
+    a.zpres[0] = p.face[4] == LBM_FACE_PRESSURE;
+    a.zpres[1] = p.face[5] == LBM_FACE_PRESSURE;
+    a.face_rho[0] = (C)p.face_rho[4];
+    a.face_rho[1] = (C)p.face_rho[5];
     const int TY = ty;
     a.tiles_x = p.nx / FTX;
     a.ntiles = a.tiles_x * (p.ny / TY);
@@ -687,14 +765,20 @@ struct FusedImpl {
     a.wall_Tw[0] = Tw0;
     a.wall_Tw[1] = Tw1;
     a.flag = flag;
+    if (a.zpres[0] || a.zpres[1]) return launch<true>(a, TY, nchunks, stream, fA, gA, fB, gB);
+    return launch<false>(a, TY, nchunks, stream, fA, gA, fB, gB);
+  }
+  template <bool OUT>
+  static hipError_t launch(const FusedArgs<C>& a, int TY, int nchunks, hipStream_t stream, const S* fA, const S* gA,
+                           S* fB, S* gB) {
     if constexpr (sizeof(S) <= 4) {
       if (TY == 16) {
-        hipLaunchKernelGGL((k_fused<S, 16>), dim3(a.ntiles * nchunks), dim3(FTX * 16), 0, stream, fA, gA, fB, gB,
-                           a);
+        hipLaunchKernelGGL((k_fused<S, 16, OUT>), dim3(a.ntiles * nchunks), dim3(FTX * 16), 0, stream, fA, gA, fB,
+                           gB, a);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_fused<S, 8>), dim3(a.ntiles * nchunks), dim3(FTX * 8), 0, stream, fA, gA, fB, gB, a);
+    hipLaunchKernelGGL((k_fused<S, 8, OUT>), dim3(a.ntiles * nchunks), dim3(FTX * 8), 0, stream, fA, gA, fB, gB, a);
     return hipGetLastError();
   }
 };

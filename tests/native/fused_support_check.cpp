@@ -19,6 +19,10 @@ int main() {
   struct Case { const char* name; lbm_params p; };
   lbm_params outlet = box(512, 512, 384, LBM_FP32_DEV, LBM_FACE_WALL);
   outlet.face[5] = LBM_FACE_PRESSURE;
+  lbm_params half_open = box(256, 256, 256, LBM_FP32_DEV, LBM_FACE_PRESSURE);
+  half_open.face[5] = LBM_FACE_PERIODIC;
+  lbm_params side_outlet = box(128, 128, 128, LBM_FP32_DEV, LBM_FACE_PRESSURE);
+  side_outlet.face[0] = side_outlet.face[1] = LBM_FACE_PRESSURE;
   const Case cases[] = {
       {"blobs_512x512x384_fp32", box(512, 512, 384, LBM_FP32_DEV, LBM_FACE_WALL)},
       {"blobs_512x512x384_fp64", box(512, 512, 384, LBM_FP64, LBM_FACE_WALL)},
@@ -26,6 +30,9 @@ int main() {
       {"ragged_96x8x8_fp32", box(96, 8, 8, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
       {"short_64x8x3_fp32", box(64, 8, 3, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
       {"outlet_512x512x384_fp32", outlet},
+      {"outlets_256x256x256_fp64", box(256, 256, 256, LBM_FP64, LBM_FACE_PRESSURE)},
+      {"half_open_256x256x256_fp32", half_open},
+      {"side_outlet_128x128x128_fp32", side_outlet},
       {"plane_4096x4096_fp64", box(4096, 4096, 8, LBM_FP64, LBM_FACE_WALL)},
       {"plane_8192x4096_fp32", box(8192, 4096, 4, LBM_FP32_DEV, LBM_FACE_WALL)},
       {"plane_8192x4096_fp64", box(8192, 4096, 4, LBM_FP64, LBM_FACE_WALL)},

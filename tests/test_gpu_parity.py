@@ -253,6 +253,25 @@ def _closed(w):
     return w
 
 
+def _flip_z(w):
+    """The same set-up mirrored in z (faces, face values, wall field, fields)."""
+    w = dict(w)
+    w["faces"] = list(w["faces"][:4]) + [w["faces"][5], w["faces"][4]]
+    w["face_T"] = list(w["face_T"][:4]) + [w["face_T"][5], w["face_T"][4]]
+    w["face_rho"] = list(w["face_rho"][:4]) + [w["face_rho"][5], w["face_rho"][4]]
+    w["Tw"] = {9 - k: v for k, v in (w.get("Tw") or {}).items()}
+    w["rho0"] = np.ascontiguousarray(w["rho0"][::-1])
+    w["T0"] = np.ascontiguousarray(w["T0"][::-1])
+    return w
+
+
+def _open_z(w):
+    """An open-box workload with its x and y faces made periodic."""
+    w = dict(w)
+    w["faces"] = [synth.PERIODIC] * 4 + list(w["faces"][4:])
+    return w
+
+
 FUSED = {
     "droplet_periodic_128x16x24": lambda: synth.droplet_periodic(nx=128, ny=16, nz=24, R0=6.0, W=5.0,
                                                                  noise=1e-6, seed=2, center=(70, 8, 12)),
@@ -262,6 +281,14 @@ FUSED = {
     # wetting ghost layer with kappa_w != 0 on both walls
     "wetting_64x16x24": lambda: _closed(synth.heated_wall(nx=64, ny=16, nz=24, R0=6.0, Tw_jitter=0.02, seed=5,
                                                           kappa_w=0.3)),
+    # constant-pressure outlets (Sec. 3.3) on z faces: wall below / outlet
+    # above with wetting and a wall temperature field, the mirror image, and
+    # outlets on both z faces
+    "heated_wall_64x16x24": lambda: synth.heated_wall(nx=64, ny=16, nz=24, R0=6.0, Tw_jitter=0.02, seed=5,
+                                                      kappa_w=0.2),
+    "outlet_below_64x16x24": lambda: _flip_z(synth.heated_wall(nx=64, ny=16, nz=24, R0=6.0, Tw_jitter=0.02,
+                                                               seed=6, kappa_w=0.2)),
+    "open_z_64x16x32": lambda: _open_z(synth.droplet_open(nx=64, ny=16, nz=32, R0=6.0)),
 }
 
 
