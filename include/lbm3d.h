@@ -125,7 +125,8 @@ lbm_status lbm_required_bytes(const lbm_params* p, size_t* state_bytes, size_t* 
  * Parameters are validated (LBM_EINVAL) and unsupported combinations
  * (walls on x/y faces) give LBM_EUNSUPPORTED.
  * A step runs as one single-pass kernel launch when x and y are periodic, z
- * is periodic or walled on both faces, nx % 64 == 0, ny % 8 == 0, nz >= 4 and
+ * is periodic or has a wall or pressure outlet on each of its two faces,
+ * nx % 64 == 0, ny % 8 == 0, nz >= 4 and
  * theta_corr = 0; otherwise as four launches of the general kernels (same
  * results to rounding).  Environment overrides read when the context is
  * created, for tests and measurements: LBM_FUSED=0 forces the general kernels,
