@@ -38,7 +38,7 @@ def parse():
                     help="other storage precisions timed on the same workload ('' for none)")
     ap.add_argument("--variant-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--accuracy-steps", type=int, default=50,
                     help="steps of the FP64-referenced accuracy check of the storage precisions (0: skip)")
     ap.add_argument("--adjoint-workload", default="heated_wall_adjoint_96",
