@@ -6,8 +6,9 @@ A step is one full time step of the method (every stage of the update) over
 the whole grid.  The default workload is the 512 x 512 x 384 closed box with
 seeded liquid blobs and a vertical temperature gradient, FP32 deviation
 storage; FP64 and FP16/BF16 storage are timed on the same workload as
-variants.  Inputs are generated on the host, uploaded once, and resident in
-HBM when the timed region starts.  The CPU baseline is the FP64 oracle on a
+variants, and the 256^3 droplet on a heated wall with an outlet in FP32 and
+FP64 as a further workload.  Inputs are generated on the host, uploaded
+once, and resident in HBM when the timed region starts.  The CPU baseline is the FP64 oracle on a
 bounded sample of the same workload.
 """
 import argparse
@@ -44,6 +45,9 @@ def parse():
     ap.add_argument("--adjoint-workload", default="heated_wall_adjoint_96",
                     help="workload of the adjoint timing ('' to skip)")
     ap.add_argument("--adjoint-precisions", default="fp64,fp32")
+    ap.add_argument("--other-workloads", default="heated_wall_256",
+                    help="further workloads timed in FP32 and FP64 storage ('' for none)")
+    ap.add_argument("--other-steps", type=int, default=50)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this size 3 times (HBM counter calibration)")
     return ap.parse_args()
@@ -262,6 +266,16 @@ def main():
         print(f"[bench] accuracy vs fp64 storage, {args.accuracy_steps} steps", file=sys.stderr, flush=True)
         accuracy = {"steps": args.accuracy_steps, "reference": "fp64 storage (= oracle to 1e-12)"}
         accuracy.update(accuracy_vs_fp64(P, torch, w, [p for p in ["fp32", "fp16", "bf16"]], args.accuracy_steps))
+    others = {}
+    for name in [v for v in args.other_workloads.split(",") if v and v != args.workload]:
+        wo = synth.named(name)
+        others[name] = {"grid": [wo["nx"], wo["ny"], wo["nz"]], "faces": wo["faces"]}
+        for prec in ("fp32", "fp64"):
+            print(f"[bench] {name} {prec}: {args.other_steps} steps", file=sys.stderr, flush=True)
+            r = time_precision(P, torch, wo, prec, args.other_steps, 5)
+            others[name][prec] = dict(mlups=round(r["mlups"], 1), ms_per_step=round(r["ms_per_step"], 4),
+                                      alg_bytes_per_cell=ALG_BYTES[prec], roofline_frac=round(r["frac"], 4))
+        del wo
     adjoint = None
     if args.adjoint_workload:
         wa = synth.named(args.adjoint_workload)
@@ -293,6 +307,7 @@ def main():
                      "achieved_on_traffic": (round(traffic / (head["ms_per_step"] * 1e-3) / 1e9, 1)
                                              if traffic else None)},
         "variants": variants,
+        "other_workloads": others,
         "accuracy": accuracy,
         "adjoint": adjoint,
         "source_hash": source_hash(),
