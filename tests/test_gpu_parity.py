@@ -327,6 +327,27 @@ def test_fused_fp32_tile_height_16(P, name, monkeypatch):
     sim.close()
 
 
+@pytest.mark.parametrize("ty", ["8", "16"])
+@pytest.mark.parametrize("name", list(FUSED))
+def test_fused_half_storage(P, name, ty, monkeypatch):
+    """FP16 and BF16 deviation storage on the single-pass kernel (both tile
+    heights, every z face kind): finite and within a loose bound of the
+    oracle after 20 steps; the measured errors are printed."""
+    monkeypatch.setenv("LBM_FUSED_TY", ty)
+    w = FUSED[name]()
+    ref = oracle_run(w, 20, record=(20,))
+    for prec, bound in (("fp16", 5e-3), ("bf16", 2e-2)):
+        sim = P.from_workload(w, precision=prec)
+        sim.step(20)
+        rho, u, T = sim.fields()
+        sim.close()
+        assert np.isfinite(rho).all() and np.isfinite(T).all()
+        er = rel_err_scalar(rho, ref[20][0])
+        eT = rel_err_scalar(T, ref[20][2])
+        _log(f"{name} {prec} ty={ty} step 20: rho {er:.3e} T {eT:.3e}")
+        assert er < bound and eT < bound
+
+
 @pytest.mark.parametrize("name", list(FUSED))
 def test_fused_matches_unfused_fp64(P, name, monkeypatch):
     w = FUSED[name]()
