@@ -90,6 +90,18 @@ __global__ void __launch_bounds__(256) k_adj_seed(C* __restrict__ lf, C* __restr
   for (int i = 0; i < 7; ++i) lg[pidx(g, 7, i, x, y, z)] = C(0);
 }
 
+// div u of a state from its stored real velocity, with the step's own
+// definition (div_u_at), for states whose fields no recomputed step wrote.
+template <typename C>
+__global__ void __launch_bounds__(256) k_div(const C* __restrict__ ureal, C* __restrict__ div_out, Geom g) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  div_out[c] = div_u_at(ureal, g, x, y, z);
+}
+
 // Reverse of S10, S9, S8, S7 and the local part of S6 at every cell x.
 //   lfi, lgi: adjoint of s_{t+1}; gA: post-Dirichlet g of s_t; gnext: g of s_{t+1}
 //   lfo, lgo: partial adjoint of the completed f, g of s_t
@@ -101,7 +113,7 @@ __global__ void __launch_bounds__(256)
                   const S* __restrict__ gA, const S* __restrict__ gnext,
                   const typename Storage<S>::C* __restrict__ rho_f, const typename Storage<S>::C* __restrict__ T_f,
                   const typename Storage<S>::C* __restrict__ ueq, const typename Storage<S>::C* __restrict__ du,
-                  const typename Storage<S>::C* __restrict__ ureal,
+                  const typename Storage<S>::C* __restrict__ divf,
                   typename Storage<S>::C* __restrict__ lfo, typename Storage<S>::C* __restrict__ lgo,
                   typename Storage<S>::C* __restrict__ a_rho, typename Storage<S>::C* __restrict__ a_T,
                   typename Storage<S>::C* __restrict__ a_ueq, typename Storage<S>::C* __restrict__ a_du,
@@ -159,22 +171,8 @@ __global__ void __launch_bounds__(256)
   C gx, gy, gz;
   local_gradT(gp, ph.vflux, ph, gx, gy, gz);
   const C rux = ux + C(0.5) * dux, ruy = uy + C(0.5) * duy, ruz = uz + C(0.5) * duz;
-  // div u from the stored real velocity (the forward's u_at values): 0
-  // beyond walls, copy beyond outlets, wrap if periodic
-  C div = C(0);
-#pragma unroll
-  for (int i = 1; i < 19; ++i) {
-    const int d = CZ[i] + 1;
-    C v = C(0);
-    if (zin[d] || g.face[CZ[i] < 0 ? 4 : 5] == FACE_PRESSURE) {
-      const int zn = zin[d] ? zl[d] : z;   // beyond an outlet: the face node's own level
-      const long long cn = nb.cell(zn, ncol(i));
-      if (CX[i]) v += C(CX[i]) * ureal[cn];
-      if (CY[i]) v += C(CY[i]) * ureal[cn + N];
-      if (CZ[i]) v += C(CZ[i]) * ureal[cn + 2 * N];
-    }
-    div += C(3) * w19<C>(i) * v;
-  }
+  // div u of the forward step (stored with the fields)
+  const C div = divf[c];
   C dp_dr, dpdT, dpdT_dr, dpdT_dT;
   pr_partials(rho, T, ph, dp_dr, dpdT, dpdT_dr, dpdT_dT);
   rb += Fbarb * (ph.cv * (rux * gx + ruy * gy + ruz * gz) + T * dpdT_dr * div);

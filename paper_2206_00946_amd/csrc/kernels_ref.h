@@ -352,6 +352,21 @@ __global__ void __launch_bounds__(256) k_force(S* __restrict__ fpop, const typen
   }
 }
 
+// Isotropic divergence of the real velocity at (x, y, z):
+// (1/c_s^2) sum_i w_i c_i . u(x + c_i), with the ghost rules of u_real_at.
+// The one definition serves the step and the adjoint's stored fields.
+template <typename C>
+__device__ __forceinline__ C div_u_at(const C* __restrict__ ureal, const Geom& g, int x, int y, int z) {
+  C div = C(0);
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    C vx, vy, vz;
+    u_real_at(ureal, g, x + CX[i], y + CY[i], z + CZ[i], vx, vy, vz);
+    div += C(3) * w19<C>(i) * (C(CX[i]) * vx + C(CY[i]) * vy + C(CZ[i]) * vz);
+  }
+  return div;
+}
+
 template <typename S>
 __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, const S* __restrict__ gA,
                                                       S* __restrict__ fB, S* __restrict__ gB,
@@ -361,7 +376,8 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
                                                       const typename Storage<S>::C* __restrict__ du,
                                                       const typename Storage<S>::C* __restrict__ ureal,
                                                       const typename Storage<S>::C* __restrict__ Th1,
-                                                      typename Storage<S>::C* __restrict__ Th2, int corr, Geom g,
+                                                      typename Storage<S>::C* __restrict__ Th2, int corr,
+                                                      typename Storage<S>::C* __restrict__ div_out, Geom g,
                                                       Phys<typename Storage<S>::C> ph) {
   using C = typename Storage<S>::C;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -374,14 +390,9 @@ __global__ void __launch_bounds__(256) k_collide_push(const S* __restrict__ fA, 
   const C T = T_f[c];
   const C ux = ueq[c], uy = ueq[c + N], uz = ueq[c + 2 * N];
   const C dux = du[c], duy = du[c + N], duz = du[c + 2 * N];
-  // isotropic divergence of the real velocity: (1/c_s^2) sum_i w_i c_i . u(x + c_i)
-  C div = C(0);
-#pragma unroll
-  for (int i = 1; i < 19; ++i) {
-    C vx, vy, vz;
-    u_real_at(ureal, g, x + CX[i], y + CY[i], z + CZ[i], vx, vy, vz);
-    div += C(3) * w19<C>(i) * (C(CX[i]) * vx + C(CY[i]) * vy + C(CZ[i]) * vz);
-  }
+  // div u, kept for the adjoint when div_out is given
+  const C div = div_u_at(ureal, g, x, y, z);
+  if (div_out) div_out[c] = div;
   C gp[7];
 #pragma unroll
   for (int i = 0; i < 7; ++i) gp[i] = Storage<S>::load(gA + pidx(g, 7, i, x, y, z));

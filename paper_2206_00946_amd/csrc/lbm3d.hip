@@ -79,12 +79,15 @@ namespace {
 long long ncells(const lbm_params& p) { return (long long)p.nx * p.ny * p.nz; }
 
 // The per-cell fields of one state in the compute precision: rho, T, psi,
-// u_eq = j/rho, Delta u = F/rho and the real velocity of eq. (5)
+// u_eq = j/rho, Delta u = F/rho, the real velocity of eq. (5) and, where a
+// buffer is given (the adjoint's stored fields), div u
 struct FieldSet {
-  void *rho, *T, *psi, *ueq, *du, *ureal;
+  void *rho, *T, *psi, *ueq, *du, *ureal, *div;
 };
 
-FieldSet ctx_fields(const lbm_ctx* ctx) { return {ctx->rho, ctx->T, ctx->psi, ctx->ueq, ctx->du, ctx->ureal}; }
+FieldSet ctx_fields(const lbm_ctx* ctx) {
+  return {ctx->rho, ctx->T, ctx->psi, ctx->ueq, ctx->du, ctx->ureal, nullptr};
+}
 
 struct Layout {
   size_t state = 0, scratch = 0;
@@ -278,7 +281,8 @@ struct Impl {
     const int corr = ctx->p.theta_corr ? (ctx->hist >= 2 ? 2 : 1) : 0;
     hipLaunchKernelGGL(k_collide_push<S>, dim3(blocks_for(geo.N)), dim3(256), 0, ctx->stream, (const S*)fs,
                        (const S*)gs, fd, gd, (const C*)F.rho, (const C*)F.T, (const C*)F.ueq, (const C*)F.du,
-                       (const C*)F.ureal, (const C*)ctx->Th[0], (C*)ctx->Th[1], corr, geo, phys_of<C>(ctx->p));
+                       (const C*)F.ureal, (const C*)ctx->Th[0], (C*)ctx->Th[1], corr, (C*)F.div, geo,
+                       phys_of<C>(ctx->p));
     if (corr) {
       std::swap(ctx->Th[0], ctx->Th[1]);
       ctx->hist = std::min(ctx->hist + 1, 2);
@@ -372,7 +376,8 @@ struct AdjPlan {
   int nsteps = 0, nseg = 0, L = 0;
   size_t fbytes = 0, gbytes = 0;
   size_t off_ck = 0, off_seg = 0, off_lf[2] = {0, 0}, off_lg[2] = {0, 0}, off_rho = 0, off_T = 0, off_div = 0,
-         off_ueq = 0, off_du = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0, off_acc = 0;
+         off_ueq = 0, off_du = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0, off_acc = 0,
+         off_fdiv = 0;
   // fields of every state of a segment, kept from its recomputation (unfused
   // steps only; the fused kernel writes no fields)
   bool cache = false;
@@ -381,7 +386,7 @@ struct AdjPlan {
   size_t state() const { return fbytes + gbytes; }
   FieldSet fields(char* base, int j) const {
     char* q = base + off_fields + (size_t)j * fslot;
-    return {q, q + fN, q + 2 * fN, q + 3 * fN, q + 6 * fN, q + 9 * fN};
+    return {q, q + fN, q + 2 * fN, q + 3 * fN, q + 6 * fN, q + 9 * fN, q + 12 * fN};
   }
 };
 
@@ -416,10 +421,11 @@ AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp, bool cache
   a.off_kap = o; o = align_up(o + 2 * P * 8);
   a.off_grad = o; o = align_up(o + P * 8);
   a.off_acc = o; o = align_up(o + 64);
+  a.off_fdiv = o; o = align_up(o + N * cs);  // div u of the state when the fields are not stored
   a.cache = cache_fields;
   if (a.cache) {
     a.fN = N * cs;
-    a.fslot = align_up(12 * a.fN);
+    a.fslot = align_up(13 * a.fN);
     a.off_fields = o; o += (size_t)a.L * a.fslot;
   }
   a.total = o;
@@ -537,8 +543,14 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
     }
     for (int j = len - 1; j >= 0; --j) {
       const S* gnext = j + 1 < len ? sg_g(j + 1) : (k + 1 < a.nseg ? ck_g(k + 1) : (const S*)ctx->gA);
-      const FieldSet F = a.cache ? a.fields(b, j) : ctx_fields(ctx);
-      if (!a.cache || j == len - 1) HIPCHK(ctx, I::prepass_to(ctx, sg_f(j), sg_g(j), F));
+      FieldSet F = a.cache ? a.fields(b, j) : ctx_fields(ctx);
+      if (!F.div) F.div = b + a.off_fdiv;
+      if (!a.cache || j == len - 1) {
+        // fields of a state no recomputed step has written: S0-S5, then div u
+        // with the step's own definition
+        HIPCHK(ctx, I::prepass_to(ctx, sg_f(j), sg_g(j), F));
+        hipLaunchKernelGGL(k_div<C>, dim3(nb), dim3(256), 0, st, (const C*)F.ureal, (C*)F.div, geo);
+      }
       const C* rho = (const C*)F.rho;
       const C* T = (const C*)F.T;
       const C* psi = (const C*)F.psi;
@@ -546,7 +558,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
       const C* du = (const C*)F.du;
       const int nx = 1 - cur;
       hipLaunchKernelGGL(k_adj_collide<S>, dim3(nb), dim3(256), 0, st, (const C*)lf[cur], (const C*)lg[cur],
-                         (const S*)sg_g(j), gnext, rho, T, ueq, du, (const C*)F.ureal, lf[nx], lg[nx], a_rho, a_T,
+                         (const S*)sg_g(j), gnext, rho, T, ueq, du, (const C*)F.div, lf[nx], lg[nx], a_rho, a_T,
                          a_ueq, a_du, a_div, geo, ph);
       hipLaunchKernelGGL(k_adj_velocity<C>, dim3(nb), dim3(256), 0, st, lf[nx], (const C*)a_div, a_ueq, a_du,
                          a_rho, rho, ueq, du, geo);
