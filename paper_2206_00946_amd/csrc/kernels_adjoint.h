@@ -6,8 +6,8 @@
 // order the kernels below run them:
 //   S9/S10 push + blend, S8 D3Q7 collision, S7 D3Q19 collision, S6 source
 //                                            -> k_adj_collide (per cell, gathers)
-//   S6 divergence stencil, S5 velocities, S4 outlet fill
-//                                            -> k_adj_velocity
+//   S6 divergence stencil, S5 velocities    -> k_adj_velocity
+//   S4 outlet fill                           -> k_adj_outlet (pressure planes)
 //   eq. (37) wetting ghost layer             -> k_adj_ghost (wall planes)
 //   S3 force stencil, S2 psi, S1 moments     -> k_adj_psi
 //   S0 thermal Dirichlet (eqs. (35)-(36))    -> k_adj_dirichlet (face planes)
@@ -233,13 +233,13 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Reverse of the divergence stencil (every reader of u at y), of S5 and of
-// the outlet fill.  On return a_ueq holds the adjoint of the momentum j,
-// a_du the adjoint of the force F, a_rho the partial adjoint of rho; at
-// outlet nodes the adjoint of f is final (lfo) and a_ueq, a_rho are zero.
+// Reverse of the divergence stencil (every reader of u at y) and of S5.  On
+// return a_ueq holds the adjoint of the momentum j, a_du the adjoint of the
+// force F, a_rho the partial adjoint of rho; k_adj_outlet then completes the
+// outlet nodes (kept apart so that this kernel's registers stay few).
 template <typename C>
 __global__ void __launch_bounds__(256)
-    k_adj_velocity(C* __restrict__ lfo, const C* __restrict__ a_div, C* __restrict__ a_ueq, C* __restrict__ a_du,
+    k_adj_velocity(const C* __restrict__ a_div, C* __restrict__ a_ueq, C* __restrict__ a_du,
                    C* __restrict__ a_rho, const C* __restrict__ rho_f, const C* __restrict__ ueq,
                    const C* __restrict__ du, Geom g) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -248,14 +248,15 @@ __global__ void __launch_bounds__(256)
   const int y = (int)((c / g.nx) % g.ny);
   const int z = (int)(c / ((long long)g.nx * g.ny));
   const long long N = g.N;
-  const Node n = classify(g, x, y, z);
+  // x and y are periodic: the bounded faces are the z planes
+  const bool wall = (z == 0 && g.face[4] == FACE_WALL) || (z == g.nz - 1 && g.face[5] == FACE_WALL);
   C ueb[3], dub[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     ueb[a] = a_ueq[c + a * N];
     dub[a] = a_du[c + a * N];
   }
-  if (!n.wall) {
+  if (!wall) {
     // readers of u(y): x = y - c_i directly, and on an outlet plane the
     // same-plane readers whose ghost neighbour is a copy of y
     const AdjNbr nb(g, x, y, z);
@@ -287,23 +288,52 @@ __global__ void __launch_bounds__(256)
     Fb[a] = dub[a] * irho;
     rb -= (ueb[a] * ueq[c + a * N] + dub[a] * du[c + a * N]) * irho;
   }
-  if (n.pressure) {
-    C fb[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i)
-      fb[i] = lfo[pidx(g, 19, i, x, y, z)] + C(CX[i]) * jb[0] + C(CY[i]) * jb[1] + C(CZ[i]) * jb[2];
-    outlet_fill_adj(fb, n.pface, Fb);
-#pragma unroll
-    for (int i = 0; i < 19; ++i) lfo[pidx(g, 19, i, x, y, z)] = fb[i];
-    jb[0] = jb[1] = jb[2] = C(0);
-    rb = C(0);  // rho = rho_out is fixed on outlet nodes
-  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     a_ueq[c + a * N] = jb[a];
     a_du[c + a * N] = Fb[a];
   }
   a_rho[c] = rb;
+}
+
+// Reverse of the outlet fill (S4) at the nodes of pressure z faces, one
+// thread per (x, y), after k_adj_velocity: f_i(x_b) entered the fill and the
+// momentum j, whose adjoint a_ueq carries; the fill's F part goes to a_du.
+// The adjoint of f becomes final there, and a_ueq, a_rho vanish (rho =
+// rho_out is fixed on outlet nodes).
+template <typename C>
+__global__ void __launch_bounds__(256) k_adj_outlet(C* __restrict__ lfo, C* __restrict__ a_ueq,
+                                                    C* __restrict__ a_du, C* __restrict__ a_rho, Geom g) {
+  const long long P = (long long)g.nx * g.ny;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P) return;
+  const int x = (int)(t % g.nx), y = (int)(t / g.nx);
+  const long long N = g.N;
+  for (int s = 0; s < 2; ++s) {
+    const int k = 4 + s;
+    if (g.face[k] != FACE_PRESSURE) continue;
+    const int z = s ? g.nz - 1 : 0;
+    const long long c = cell_index(g, x, y, z);
+    C jb[3], Fb[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      jb[a] = a_ueq[c + a * N];
+      Fb[a] = a_du[c + a * N];
+    }
+    C fb[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+      fb[i] = lfo[pidx(g, 19, i, x, y, z)] + C(CX[i]) * jb[0] + C(CY[i]) * jb[1] + C(CZ[i]) * jb[2];
+    outlet_fill_adj(fb, k, Fb);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) lfo[pidx(g, 19, i, x, y, z)] = fb[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      a_ueq[c + a * N] = C(0);
+      a_du[c + a * N] = Fb[a];
+    }
+    a_rho[c] = C(0);
+  }
 }
 
 // Reverse of the wetting ghost layer of eq. (37) on each wall face, one

@@ -501,6 +501,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   const size_t NP = (size_t)p.nz * plane_pitch(p.nx, p.ny);
   const size_t fsz = 19 * NP * sizeof(S), gsz = 7 * NP * sizeof(S);
   const bool walls = p.face[4] == LBM_FACE_WALL || p.face[5] == LBM_FACE_WALL;
+  const bool outlets = p.face[4] == LBM_FACE_PRESSURE || p.face[5] == LBM_FACE_PRESSURE;
 
   // forward pass with checkpoints; J = M(t0) - M(t0 + N)
   double s0[RED_VALUES], s1[RED_VALUES];
@@ -560,8 +561,9 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
       hipLaunchKernelGGL(k_adj_collide<S>, dim3(nb), dim3(256), 0, st, (const C*)lf[cur], (const C*)lg[cur],
                          (const S*)sg_g(j), gnext, rho, T, ueq, du, (const C*)F.div, lf[nx], lg[nx], a_rho, a_T,
                          a_ueq, a_du, a_div, geo, ph);
-      hipLaunchKernelGGL(k_adj_velocity<C>, dim3(nb), dim3(256), 0, st, lf[nx], (const C*)a_div, a_ueq, a_du,
+      hipLaunchKernelGGL(k_adj_velocity<C>, dim3(nb), dim3(256), 0, st, (const C*)a_div, a_ueq, a_du,
                          a_rho, rho, ueq, du, geo);
+      if (outlets) hipLaunchKernelGGL(k_adj_outlet<C>, dim3(npb), dim3(256), 0, st, lf[nx], a_ueq, a_du, a_rho, geo);
       if (walls)
         hipLaunchKernelGGL(k_adj_ghost<C>, dim3(npb), dim3(256), 0, st, (const C*)a_du, psi, gadj, ax, ay, kap, geo,
                            ph);
