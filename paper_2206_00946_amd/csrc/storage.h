@@ -42,14 +42,10 @@ struct Storage<bf16> {
   static __device__ __forceinline__ float load(const bf16* p) {
     return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
   }
+  // the hardware conversion (v_cvt_pk_bf16_f32: round to nearest even, NaN
+  // stays NaN)
   static __device__ __forceinline__ void store(bf16* p, float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
-      p->bits = static_cast<uint16_t>((u >> 16) | 0x40u);  // keep NaN a NaN
-      return;
-    }
-    u += 0x7fffu + ((u >> 16) & 1u);
-    p->bits = static_cast<uint16_t>(u >> 16);
+    p->bits = __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
   }
 };
 
