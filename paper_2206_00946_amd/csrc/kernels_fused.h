@@ -29,6 +29,7 @@
 // step is exactly one launch of this kernel.
 #pragma once
 
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -716,6 +717,24 @@ inline int fused_tile_height(int precision) {
     if (std::atoi(ev) == 16) return 16;
   }
   return 8;
+}
+
+// z planes per workgroup.  One workgroup runs on a compute unit at a time,
+// so a launch takes ceil(workgroups / 256) rounds of one chunk's march: the
+// chunk count (chunks of >= 8 planes) with the least rounds x (planes per
+// chunk + 8) is taken, the 8 standing for a march's halo planes, start and
+// end.
+inline int fused_chunk_planes(int nx, int ny, int nz, int ty) {
+  const long long ntiles = (long long)(nx / FTX) * (ny / ty);
+  long long nchunks = 1, best = -1;
+  for (long long n = 1; n <= std::max(1, nz / 8); ++n) {
+    const long long cost = (ntiles * n + 255) / 256 * ((nz + n - 1) / n + 8);
+    if (best < 0 || cost < best) {
+      best = cost;
+      nchunks = n;
+    }
+  }
+  return (int)((nz + nchunks - 1) / nchunks);
 }
 
 inline bool fused_supported(const lbm_params& p, int ty) {

@@ -699,21 +699,7 @@ lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_by
   ctx->fused_ok = fused_supported(*p, ctx->fused_ty) && p->theta_corr == 0;
   if (const char* ev = std::getenv("LBM_FUSED_MAP")) ctx->fused_map = std::atoi(ev) == 1;
   {
-    // z chunks per tile column.  One workgroup runs on a compute unit at a
-    // time, so a launch takes ceil(workgroups / 256) rounds of one chunk's
-    // march: take the chunk count (chunks of >= 8 planes) with the least
-    // rounds x (planes per chunk + 8), the 8 standing for a march's halo
-    // planes, start and end
-    const long long ntiles = (long long)(p->nx / FTX) * (p->ny / ctx->fused_ty);
-    long long nchunks = 1, best = -1;
-    for (long long n = 1; n <= std::max(1, p->nz / 8); ++n) {
-      const long long cost = (ntiles * n + 255) / 256 * ((p->nz + n - 1) / n + 8);
-      if (best < 0 || cost < best) {
-        best = cost;
-        nchunks = n;
-      }
-    }
-    ctx->fused_chunk = (int)((p->nz + nchunks - 1) / nchunks);
+    ctx->fused_chunk = fused_chunk_planes(p->nx, p->ny, p->nz, ctx->fused_ty);
     if (const char* ev = std::getenv("LBM_FUSED")) {
       if (ev[0] == '0') ctx->fused_ok = false;
     }

@@ -2,7 +2,8 @@
 x/y periodic, z periodic or bounded by walls or pressure outlets (both z
 faces bounded), tile-divisible x/y, at least 4 planes,
 and direction planes small enough for the kernel's 32-bit buffer offsets
-(larger planes run the unfused kernels, which index with 64 bits)."""
+(larger planes run the unfused kernels, which index with 64 bits), and the z
+planes per workgroup the context picks."""
 import os
 import shutil
 import subprocess
@@ -19,6 +20,10 @@ EXPECTED = {
     "plane_4096x4096_fp64": 1, "plane_8192x4096_fp32": 1, "plane_8192x4096_fp64": 0,
     "plane_8192x8192_fp32": 0,
     "ty16_512x512x384_fp32": 1, "ty16_512x512x384_fp64": 0, "ty16_64x8x8_fp32": 0,
+    # z planes per workgroup: one round of 256 workgroups where the tiles
+    # allow (256^3: 128 tiles x 2 chunks), whole columns at 512^2 (512 tiles)
+    "chunk_512x512x384": 384, "chunk_256x256x256": 128, "chunk_128x128x128": 16,
+    "chunk_64x16x24": 8, "chunk_64x8x4": 4,
 }
 
 
