@@ -185,6 +185,26 @@ def test_error_paths(P):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("setup", ["periodic", "wall_outlet"])
+def test_nonphysical_state_on_the_single_pass_kernel(P, prec, setup):
+    """A density beyond the psi^2 > 0 range is reported (LBM_ENONPHYS) by the
+    single-pass kernel too, for closed and outlet z faces."""
+    if setup == "periodic":
+        w = synth.droplet_periodic(nx=64, ny=8, nz=8, R0=2.0, noise=0.0)
+    else:
+        w = synth.heated_wall(nx=64, ny=8, nz=8, R0=3.0)
+    w["rho0"][4, 4, 30] = 9.5
+    po = oracle_params(w)
+    f, g = O.init_populations(w["rho0"], w["T0"], po)
+    assert O.macroscopic(f, g, po)["bad"].any()
+    sim = P.from_workload(w, precision=prec)
+    with pytest.raises(P.LbmError) as e:
+        sim.step(1)
+    assert e.value.status == 4            # LBM_ENONPHYS
+    sim.close()
+
+
 # ---------------------------------------------------------------- full sizes
 
 FULL = ["droplet_open_128", "heated_wall_256", "heated_wall_adjoint_96", "blobs_closed_512x512x384"]
