@@ -1,7 +1,8 @@
 // Unfused kernels of the coupled step, one pass per stage of the update
 // (Huang, Wang, He & Huang, arXiv 2206.00946, Sec. 2-3):
-//   k_thermal_dirichlet  -- eqs. (35)-(36) at the nodes of bounded faces (in place)
-//   k_macro              -- rho, T (eq. (3), T = sum g), psi (eq. (7)), flag
+//   k_macro              -- eqs. (35)-(36) at the nodes of bounded faces (g in
+//                           place), rho, T (eq. (3), T = sum g), psi (eq. (7)),
+//                           flag
 //   k_force              -- interaction force (eq. (6)) with ghost rules,
 //                           outlet fill (Sec. 3.3), u_eq and du (eqs. (3)-(5))
 //   k_collide_push       -- div u, local grad T, Fbar (eq. (15)), D3Q19 and
@@ -156,44 +157,13 @@ __device__ __forceinline__ void u_real_at(const C* __restrict__ ureal, const Geo
 
 // ---------------------------------------------------------------- kernels
 
+// S0-S2 per node.  At a node of a bounded face, g is first completed in
+// place by eqs. (35)-(36): g_i(x_b) = w_i T_b + g_i(x_f) - w_i T(x_f) from
+// the inward (diagonal at edges) neighbour x_f, which lies on no bounded
+// face (bounded axes have >= 3 cells), so no thread reads a g another
+// thread writes.  T is the sum of the stored (rounded) g.
 template <typename S>
-__global__ void __launch_bounds__(256) k_thermal_dirichlet(S* __restrict__ gpop, Geom g,
-                                                           Faces<typename Storage<S>::C> fc,
-                                                           Phys<typename Storage<S>::C> ph) {
-  using C = typename Storage<S>::C;
-  const int k = blockIdx.y;
-  if (g.face[k] == FACE_PERIODIC) return;
-  const int a = k >> 1;
-  const int nu = a == 0 ? g.ny : g.nx;
-  const int nv = a == 2 ? g.ny : g.nz;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)nu * nv) return;
-  const int u = (int)(t % nu), v = (int)(t / nu);
-  const int fixed = (k & 1) ? (a == 0 ? g.nx : (a == 1 ? g.ny : g.nz)) - 1 : 0;
-  int x, y, z;
-  if (a == 0) { x = fixed; y = u; z = v; }
-  else if (a == 1) { x = u; y = fixed; z = v; }
-  else { x = u; y = v; z = fixed; }
-  const Node n = classify(g, x, y, z);
-  if (n.prio != k) return;  // handled by the launch slice of its priority face
-  C gf[7];
-  C sum = C(0);
-#pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    gf[i] = Storage<S>::load(gpop + pidx(g, 7, i, x + n.ix, y + n.iy, z + n.iz));
-    sum += gf[i];
-  }
-  const C Tb = boundary_T(g, fc, n.prio, x, y);
-  const C d = Tb - ph.T_ref - sum;  // T_b - T(x_f), both relative to T_ref
-#pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    const C w = i == 0 ? ph.w0 : ph.w1;
-    Storage<S>::store(gpop + pidx(g, 7, i, x, y, z), gf[i] + w * d);
-  }
-}
-
-template <typename S>
-__global__ void __launch_bounds__(256) k_macro(const S* __restrict__ fpop, const S* __restrict__ gpop,
+__global__ void __launch_bounds__(256) k_macro(const S* __restrict__ fpop, S* __restrict__ gpop,
                                                typename Storage<S>::C* __restrict__ rho_out,
                                                typename Storage<S>::C* __restrict__ T_out,
                                                typename Storage<S>::C* __restrict__ psi_out,
@@ -206,13 +176,33 @@ __global__ void __launch_bounds__(256) k_macro(const S* __restrict__ fpop, const
   const int x = (int)(c % g.nx);
   const int y = (int)((c / g.nx) % g.ny);
   const int z = (int)(c / ((long long)g.nx * g.ny));
+  const Node n = classify(g, x, y, z);
   C sf = C(0), sg = C(0);
 #pragma unroll
   for (int i = 0; i < 19; ++i) sf += Storage<S>::load(fpop + pidx(g, 19, i, x, y, z));
+  if (n.count > 0) {
+    C gf[7];
+    C sum = C(0);
 #pragma unroll
-  for (int i = 0; i < 7; ++i) sg += Storage<S>::load(gpop + pidx(g, 7, i, x, y, z));
+    for (int i = 0; i < 7; ++i) {
+      gf[i] = Storage<S>::load(gpop + pidx(g, 7, i, x + n.ix, y + n.iy, z + n.iz));
+      sum += gf[i];
+    }
+    const C Tb = boundary_T(g, fc, n.prio, x, y);
+    const C d = Tb - ph.T_ref - sum;  // T_b - T(x_f), both relative to T_ref
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      const C w = i == 0 ? ph.w0 : ph.w1;
+      S v;
+      Storage<S>::store(&v, gf[i] + w * d);
+      Storage<S>::store(gpop + pidx(g, 7, i, x, y, z), Storage<S>::load(&v));
+      sg += Storage<S>::load(&v);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) sg += Storage<S>::load(gpop + pidx(g, 7, i, x, y, z));
+  }
   C rho = ph.rho_ref + sf;
-  const Node n = classify(g, x, y, z);
   if (n.pressure) rho = fc.face_rho[n.prio];
   const C T = ph.T_ref + sg;
   const C rad = psi_radicand(rho, T, ph);

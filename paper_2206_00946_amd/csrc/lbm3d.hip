@@ -237,28 +237,15 @@ template <typename S>
 struct Impl {
   using C = typename Storage<S>::C;
 
-  static hipError_t thermal_dirichlet(lbm_ctx* ctx, S* g) {
-    const lbm_params& p = ctx->p;
-    const Geom geo = geom_of(p);
-    const long long plane = std::max({(long long)p.nx * p.ny, (long long)p.nx * p.nz, (long long)p.ny * p.nz});
-    dim3 grid(blocks_for(plane), 6);
-    hipLaunchKernelGGL(k_thermal_dirichlet<S>, grid, dim3(256), 0, ctx->stream, g, geo, faces_of<C>(ctx),
-                       phys_of<C>(p));
-    return hipGetLastError();
-  }
-
-  // S0-S5 on the state (f, g): complete its boundary nodes in place and fill
-  // rho, T, psi, u_eq, du.
   // S0-S5 of the state (f, g) into the field set F: Dirichlet completion of g
-  // in place, then rho, T, psi and the velocities
+  // and rho, T, psi (k_macro), then the outlet fill of f and the velocities
+  // (k_force), both in place on the state
   static hipError_t prepass_to(lbm_ctx* ctx, S* f, S* g, const FieldSet& F) {
     const lbm_params& p = ctx->p;
     const Geom geo = geom_of(p);
     const Phys<C> ph = phys_of<C>(p);
     const Faces<C> fc = faces_of<C>(ctx);
     const unsigned nb = blocks_for(geo.N);
-    hipError_t e = thermal_dirichlet(ctx, g);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_macro<S>, dim3(nb), dim3(256), 0, ctx->stream, f, g, (C*)F.rho, (C*)F.T, (C*)F.psi,
                        ctx->flag, geo, fc, ph);
     hipLaunchKernelGGL(k_force<S>, dim3(nb), dim3(256), 0, ctx->stream, f, (const C*)F.rho, (const C*)F.psi,
