@@ -51,7 +51,6 @@ template <typename C>
 struct FusedArgs {
   Phys<C> ph;
   int nx, ny, nz;
-  long long N;
   long long pitch;  // elements from one direction plane to the next
   int zbound;      // 1: z bounded by the faces at z = 0 and z = nz - 1; 0: periodic z
   int zpres[2];    // bounded face is a pressure outlet (1) or a no-slip wall (0)
@@ -205,7 +204,6 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   }
   const int z0 = chunk * a.chunk, z1 = min(a.nz, z0 + a.chunk);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const long long N = a.N;
   const long long PS = a.pitch;  // population planes: direction i of level z starts at (z*Q + i)*PS
   // 16-bit storage: tiles start 2 columns past a 64-column boundary, so that
   // the side halo columns lie in 128-byte lines the tile loads itself (a row
@@ -773,7 +771,6 @@ struct FusedImpl {
     a.nx = p.nx;
     a.ny = p.ny;
     a.nz = p.nz;
-    a.N = (long long)p.nx * p.ny * p.nz;
     a.pitch = plane_pitch(p.nx, p.ny);
     a.zbound = p.face[4] != LBM_FACE_PERIODIC;
     a.zpres[0] = p.face[4] == LBM_FACE_PRESSURE;
