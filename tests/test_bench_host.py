@@ -1,5 +1,8 @@
 """Host-side pieces of bench.py: the source hash that ties the committed
-traffic counters to the step kernel ignores comments but not code."""
+traffic counters to the step kernel ignores comments but not code, and the
+one-GPU guard."""
+import os
+
 import bench
 
 
@@ -17,3 +20,17 @@ def test_comment_edit_keeps_hash_code_edit_changes_it():
 def test_fused_kernel_hash_is_stable():
     assert bench.fused_kernel_hash() == bench.fused_kernel_hash()
     assert len(bench.fused_kernel_hash()) == 16
+
+
+def test_more_than_one_gpu_is_refused():
+    """The library runs on one GPU: --gpus N > 1 prints a JSON error and exits 2
+    before touching a device."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
