@@ -1,7 +1,8 @@
 """Checkpoint and resume through the C ABI (lbm_save / lbm_load): a context
 restored from an image continues bitwise like the context that wrote it —
 unfused kernels with a wall temperature field, wetting and an outlet, the
-single-pass kernel in FP32, and vartheta = 1 with its temperature history —
+single-pass kernel in FP32 and (outlet variant) in BF16, and vartheta = 1
+with its temperature history —
 and malformed or mismatched images are refused."""
 import sys
 
@@ -40,6 +41,8 @@ CASES = {
                                                               rmax=8.0, seed=9), "fp32"),
     "droplet_open_37x34x29_theta1_fp64": (lambda: _theta1(synth.droplet_open(nx=37, ny=34, nz=29, R0=9.0)),
                                           "fp64"),
+    "heated_wall_64x16x24_bf16": (lambda: synth.heated_wall(nx=64, ny=16, nz=24, R0=6.0, Tw_jitter=0.02,
+                                                            kappa_w=0.2), "bf16"),
 }
 
 
