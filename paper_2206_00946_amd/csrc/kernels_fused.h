@@ -190,8 +190,16 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   const int tx = tid % TX, ty = tid / TX;
   int b = blockIdx.x;
   const int nb = gridDim.x;
-  // consecutive tiles on one XCD (blocks are dealt to the 8 XCDs round-robin)
-  if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+  // Blocks are dealt to the 8 XCDs round-robin and run in rounds of 256, one
+  // workgroup per compute unit.  Each XCD gets runs of consecutive tiles; with
+  // several rounds, the runs of one round are adjacent bands (XCD k takes
+  // tiles 32k .. 32k + 31 of the round's 256), so the halo rows at a band's
+  // edge are loaded at the same time by the neighbouring XCD and come from
+  // the shared last-level cache rather than from HBM (FP32 step 5.04 -> 4.97
+  // ms, FP64 11.45 -> 10.99 ms at 512 x 512 x 384 against one run of 64
+  // tiles per XCD spanning both rounds)
+  if (nb % 256 == 0 && nb > 256) b = (b >> 8) * 256 + (b & 7) * 32 + ((b & 255) >> 3);
+  else if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
   const int tile = b % a.ntiles, chunk = b / a.ntiles;
   int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
   if (a.xcd_blocks) {
