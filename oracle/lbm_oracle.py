@@ -48,7 +48,9 @@ complex inputs); comparisons only ever see the real parts of masks that
 do not depend on the state.
 
 Parity status: every function is pinned by tests under ``tests/`` (algebraic
-identities, invariants, closed forms, brute force, printed special cases),
+identities, invariants, closed forms, brute force, printed special cases;
+the relaxation rates, the viscosity of Sec. 4, the no-slip wall reading and
+both terms of the temperature source of eq. (15) by the transport pins),
 except the physics-only quantities listed in the design notes (coexistence
 densities of the running model, surface tension, evaporation rate), which
 are "parity unpinned" beyond loose physical checks.
