@@ -6,9 +6,10 @@
 // no-slip wall (ghost psi of eq. (37): the first interior layer plus kappa_w
 // times the tangential difference magnitude on the wall layer) or a
 // constant-pressure outlet (Sec. 3.3: rho = rho_out on the face, unknown
-// populations filled, ghost psi and u copies of the face node).  nx must be
-// a multiple of 64 and ny a multiple of the tile height.  Other set-ups use
-// the unfused kernels.
+// populations filled, ghost psi and u copies of the face node).  ny must be
+// a multiple of the tile height; nx is any size >= 8 (the last tile column of
+// a ragged nx is partly idle, see below).  Other set-ups use the unfused
+// kernels.
 //
 // A workgroup owns a 64 x TY column tile (one wavefront per row, one thread
 // per column) and marches through z.  For every plane p it loads the
@@ -27,6 +28,13 @@
 // Dirichlet temperatures on bounded-face nodes (eqs. (35)-(36)) are applied
 // to the values loaded for a face plane, from the next plane inward; a time
 // step is exactly one launch of this kernel.
+//
+// Ragged nx: tiles start every 64 columns and the last one holds
+// W = nx - x0 < 64 cells.  Its lanes tx >= W take the cells that follow
+// periodically (x0 + tx mod nx), so the stencils of the W active cells read
+// the right neighbours from LDS; those lanes compute but store nothing, except
+// that lane W finishes the +x D3Q7 link coming from the active cell W-1 (its
+// destination, cell x0 + W mod nx, gets that link from no other tile).
 #pragma once
 
 #include <algorithm>
@@ -212,6 +220,10 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   }
   const int z0 = chunk * a.chunk, z1 = min(a.nz, z0 + a.chunk);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
+  // active columns of this tile (all 64 unless nx is ragged); lanes from W on
+  // are idle duplicates of the cells that follow
+  const int W = min(TX, nx - x0);
+  const bool act = tx < W;
   const long long PS = a.pitch;  // population planes: direction i of level z starts at (z*Q + i)*PS
   // 16-bit storage: tiles start 2 columns past a 64-column boundary, so that
   // the side halo columns lie in 128-byte lines the tile loads itself (a row
@@ -220,7 +232,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   // than it saves (FP32 +4 %, FP64 +9 %), so those tiles stay aligned.
   constexpr int XS = sizeof(S) == 2 ? 2 : 0;
   x0 += XS;
-  const int x = XS ? wrapn(x0 + tx, nx) : x0 + tx, y = y0 + ty;
+  const int x = (x0 + tx) % nx, y = y0 + ty;
   constexpr unsigned ES = sizeof(S);
   const unsigned col = (unsigned)(x + nx * y);
   const unsigned colb = col * ES;
@@ -239,7 +251,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   int hex, hey;
   TL::halo_cell(tid < TL::NH ? tid : 0, hex, hey);
   const bool has_halo = tid < TL::NH;
-  const unsigned hcol = (unsigned)(wrapn(x0 + hex - 2, nx) + nx * wrapn(y0 + hey - 2, ny));
+  const unsigned hcol = (unsigned)((x0 + hex - 2 + nx) % nx + nx * wrapn(y0 + hey - 2, ny));
   const unsigned hcolb = hcol * ES;
   const int he = hey * EX + hex;
   int rdir;
@@ -278,7 +290,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
 #pragma unroll
     for (int i = 1; i <= 4; ++i) {
       const int sx = tx - CX[i], sy = ty - CY[i];
-      if (sx < 0 || sx >= TX || sy < 0 || sy >= TY) continue;
+      // the source must be an active cell of this tile
+      if (sx < 0 || sx >= W || sy < 0 || sy >= TY) continue;
       const C gs = s_gs[i - 1][sy * TX + sx];
       st_at(gz, G7, colb, i * PB, pend_g[i - 1] + (gs - pend_g[i - 1]) * (inv_cv * rcp(pend_rho)));
     }
@@ -537,7 +550,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         s_u[0][e_own] = ub[0];
         s_u[1][e_own] = ub[1];
         s_u[2][e_own] = ub[2];
-        if (ST || (q >= z0 && q < z1)) {
+        if (act && (ST || (q >= z0 && q < z1))) {
           if (pres_q) {
             // Sec. 3.3: the unknown populations of the outlet node
             const C F3[3] = {Fx, Fy, Fz};
@@ -603,9 +616,11 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       S* pm = fB + PS * 19 * (p - 2);
       S* p0 = fB + PS * 19 * (p - 1);
       S* pp = fB + PS * 19 * p;
+      if (act) {
 #pragma unroll
-      for (int i = kEarlyF; i < 19; ++i)
-        st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+        for (int i = kEarlyF; i < 19; ++i)
+          st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+      }
       __builtin_amdgcn_s_setprio(0);
     }
     // ---------------------------------------------------------------- divergence contributions of u(q)
@@ -636,7 +651,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       const C Fbar = rho * ph.cv * (ua[0] * gx + ua[1] * gy + ua[2] * gz) + T * pr_dpdT(rho, T, ph) * d0;
       const C og0 = ga[0];
       collide7(ga, Fbar, vf, ph);
-      st_at(gB + PS * 7 * zr, G7, colb, 0u, og0 + (ga[0] - og0) * (inv_cv * rcp(rho)));
+      if (act) st_at(gB + PS * 7 * zr, G7, colb, 0u, og0 + (ga[0] - og0) * (inv_cv * rcp(rho)));
       // +z: destination is plane r+1 of this column (old value in gb)
       {
         int zd = zr + 1;
@@ -644,7 +659,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         if (!ST && zd >= nz) {
           if (a.zbound) ok = false; else zd = 0;
         }
-        if (ok)
+        if (ok && act)
           st_at(gB + PS * 7 * zd, G7, colb, 5 * PB, gb[5] + (ga[5] - gb[5]) * (inv_cv * rcp(rho_b)));
       }
       // -z: destination is plane r-1 of this column (old value kept from last iteration)
@@ -654,7 +669,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         if (!ST && zd < 0) {
           if (a.zbound) ok = false; else zd = nz - 1;
         }
-        if (ok)
+        if (ok && act)
           st_at(gB + PS * 7 * zd, G7, colb, 6 * PB, g6_old + (ga[6] - g6_old) * (inv_cv * rcp(pend_rho)));
       }
       const int rs = (k + 2) & 3;  // rho / ring slot of plane r
@@ -663,7 +678,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         const int dx = tx + CX[i], dy = ty + CY[i];
         if (dx >= 0 && dx < TX && dy >= 0 && dy < TY) {
           s_gs[i - 1][tid] = ga[i];
-        } else {
+        } else if (act) {
           const int slot = i == 1 ? ty : (i == 2 ? TY + ty : (i == 3 ? 2 * TY + tx : 2 * TY + TX + tx));
           const C gold = s_gr[rs][slot];
           const C rd = s_rho[rs][e_own + CX[i] + CY[i] * EX];
@@ -736,7 +751,7 @@ inline int fused_tile_height(int precision) {
 // chunk + 8) is taken, the 8 standing for a march's halo planes, start and
 // end.
 inline int fused_chunk_planes(int nx, int ny, int nz, int ty) {
-  const long long ntiles = (long long)(nx / FTX) * (ny / ty);
+  const long long ntiles = (long long)((nx + FTX - 1) / FTX) * (ny / ty);
   long long nchunks = 1, best = -1;
   for (long long n = 1; n <= std::max(1, nz / 8); ++n) {
     const long long cost = (ntiles * n + 255) / 256 * ((nz + n - 1) / n + 8);
@@ -755,7 +770,7 @@ inline bool fused_supported(const lbm_params& p, int ty) {
   const bool zbound = p.face[4] != LBM_FACE_PERIODIC && p.face[5] != LBM_FACE_PERIODIC;
   if (!zper && !zbound) return false;
   if (ty != 8 && (ty != 16 || p.precision == LBM_FP64)) return false;
-  if (p.nx % FTX != 0 || p.ny % ty != 0) return false;
+  if (p.nx < 8 || p.ny % ty != 0) return false;
   if (p.nz < 4) return false;
   // buffer offsets are 32-bit: the 19 direction planes of one level must span
   // less than the offset that marks a halo lane without a cell (0xFFFFFF00)
@@ -784,7 +799,7 @@ struct FusedImpl {
     a.face_rho[0] = (C)p.face_rho[4];
     a.face_rho[1] = (C)p.face_rho[5];
     const int TY = ty;
-    a.tiles_x = p.nx / FTX;
+    a.tiles_x = (p.nx + FTX - 1) / FTX;
     a.ntiles = a.tiles_x * (p.ny / TY);
     a.chunk = chunk_planes > 0 ? chunk_planes : p.nz;
     const int nchunks = (p.nz + a.chunk - 1) / a.chunk;

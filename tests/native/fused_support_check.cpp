@@ -28,6 +28,7 @@ int main() {
       {"blobs_512x512x384_fp64", box(512, 512, 384, LBM_FP64, LBM_FACE_WALL)},
       {"periodic_64x8x4_fp16", box(64, 8, 4, LBM_FP16_DEV, LBM_FACE_PERIODIC)},
       {"ragged_96x8x8_fp32", box(96, 8, 8, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
+      {"narrow_4x8x8_fp32", box(4, 8, 8, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
       {"short_64x8x3_fp32", box(64, 8, 3, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
       {"outlet_512x512x384_fp32", outlet},
       {"outlets_256x256x256_fp64", box(256, 256, 256, LBM_FP64, LBM_FACE_PRESSURE)},

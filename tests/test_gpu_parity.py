@@ -80,9 +80,9 @@ def test_fp32_deviation_parity_small(P, name):
     ref = oracle_run(w, steps, record=(1, steps))
     sim = P.from_workload(w, precision="fp32")
     sim.step(1)
-    _compare(f"{name} fp32 step 1", sim.fields(), ref[1], 1e-5, 1e-3, 1e-5)
+    _compare(f"{name} fp32 step 1", sim.fields(), ref[1], 1e-5, 1e-5, 1e-5)
     sim.step(steps - 1)
-    _compare(f"{name} fp32 step {steps}", sim.fields(), ref[steps], 1e-4, 2e-2, 1e-4)
+    _compare(f"{name} fp32 step {steps}", sim.fields(), ref[steps], 1e-4, 2e-4, 1e-4)
     sim.close()
 
 
@@ -232,6 +232,45 @@ def _sample_points(w, rng, n_random=6):
 
 @pytest.mark.parametrize("name", FULL)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_multi_step(P, name, prec):
+    """Full-size workloads in the launch configuration the bench times, 5
+    steps on the GPU, compared at sampled cells with the oracle run for 5
+    steps on the surrounding 65^3 block: a cell 31 or more cells from every
+    cut side of the block evolves exactly as in the full domain (one step
+    reaches 6 cells, the wetting ghost one more).  The block's cut sides are
+    artificial and may leave the physical range; the compared cells never
+    see them within the 5 steps."""
+    k = 5
+    _log(f"[full size x{k}] {name} {prec}: generating")
+    w = _full_workload(name)
+    rng = np.random.default_rng(11)
+    pts = _sample_points(w, rng, n_random=3)[:10]
+    _log(f"[full size x{k}] {name} {prec}: GPU steps")
+    sim = P.from_workload(w, precision=prec)
+    sim.step(k)
+    rho, u, T = sim.fields()
+    sim.close()
+    del sim
+    tol_r, tol_u, tol_T = (TOL64, 1e-13, TOL64) if prec == "fp64" else (2e-5, 1e-5, 2e-5)
+    worst = np.zeros(3)
+    for (x, y, z) in pts:
+        b = sub_block(w, (x, y, z), half=6 * k + 2, margin=6 * k + 1)
+        with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+            ref = oracle_run(b, k, record=(k,), check=False)[k]
+        lx, ly, lz = b["local"]
+        for a in range(3):
+            assert b["valid"][a][0] <= b["local"][a] < b["valid"][a][1]
+        er = abs(rho[z, y, x] - ref[0][lz, ly, lx]) / abs(ref[0][lz, ly, lx])
+        eT = abs(T[z, y, x] - ref[2][lz, ly, lx]) / abs(ref[2][lz, ly, lx])
+        eu = np.abs(u[:, z, y, x] - ref[1][:, lz, ly, lx]).max()
+        worst = np.maximum(worst, (er, eu, eT))
+        assert er < tol_r and eT < tol_T and eu < tol_u, ((x, y, z), er, eu, eT)
+    _log(f"[full size x{k}] {name} {prec}: {len(pts)} cells ok; worst rho {worst[0]:.2e} u {worst[1]:.2e} "
+         f"T {worst[2]:.2e}")
+
+
+@pytest.mark.parametrize("name", FULL)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_full_size_sampled(P, name, prec):
     """Full-size workloads, the launch configuration the bench times: one step
     on the GPU, compared at sampled cells with the oracle run on the
@@ -309,6 +348,16 @@ FUSED = {
     "outlet_below_64x16x24": lambda: _flip_z(synth.heated_wall(nx=64, ny=16, nz=24, R0=6.0, Tw_jitter=0.02,
                                                                seed=6, kappa_w=0.2)),
     "open_z_64x16x32": lambda: _open_z(synth.droplet_open(nx=64, ny=16, nz=32, R0=6.0)),
+    # ragged nx: a last tile column with 32, 36 and 40 active cells (and one
+    # below the tile width), idle lanes holding the periodic continuation
+    "droplet_periodic_96x16x24": lambda: synth.droplet_periodic(nx=96, ny=16, nz=24, R0=6.0, W=5.0, noise=1e-6,
+                                                                seed=3, center=(80, 8, 12)),
+    "heated_wall_100x16x20": lambda: synth.heated_wall(nx=100, ny=16, nz=20, R0=6.0, Tw_jitter=0.02, seed=7,
+                                                       kappa_w=0.2),
+    "blobs_closed_40x16x24": lambda: synth.blobs_closed(nx=40, ny=16, nz=24, mean_blobs=2, rmin=4.0, rmax=6.0,
+                                                        seed=9),
+    "heated_wall_8x8x12": lambda: synth.heated_wall(nx=8, ny=8, nz=12, R0=2.5, Tw_jitter=0.02, seed=8,
+                                                    kappa_w=0.3),
 }
 
 
@@ -326,11 +375,11 @@ def test_fused_parity(P, name, prec, chunk, monkeypatch):
     _log(f"[fused] {name} {prec} chunk={chunk or 'all'}")
     ref = oracle_run(w, steps, record=(1, steps))
     sim = P.from_workload(w, precision=prec)
-    tol = (TOL64, TOL64, TOL64) if prec == "fp64" else (1e-5, 1e-3, 1e-5)
+    tol = (TOL64, TOL64, TOL64) if prec == "fp64" else (1e-5, 1e-5, 1e-5)
     sim.step(1)
     _compare(f"{name} {prec} step 1", sim.fields(), ref[1], *tol)
     sim.step(steps - 1)
-    tol = (TOL64, TOL64, TOL64) if prec == "fp64" else (1e-4, 2e-2, 1e-4)
+    tol = (TOL64, TOL64, TOL64) if prec == "fp64" else (1e-4, 2e-4, 1e-4)
     _compare(f"{name} {prec} step {steps}", sim.fields(), ref[steps], *tol)
     sim.close()
 
@@ -343,7 +392,7 @@ def test_fused_fp32_tile_height_16(P, name, monkeypatch):
     ref = oracle_run(w, 20, record=(20,))
     sim = P.from_workload(w, precision="fp32")
     sim.step(20)
-    _compare(f"{name} fp32 ty=16 step 20", sim.fields(), ref[20], 1e-4, 2e-2, 1e-4)
+    _compare(f"{name} fp32 ty=16 step 20", sim.fields(), ref[20], 1e-4, 2e-4, 1e-4)
     sim.close()
 
 
@@ -379,6 +428,80 @@ def test_fused_matches_unfused_fp64(P, name, monkeypatch):
         out.append(sim.fields())
         sim.close()
     _compare(f"{name} fused vs unfused", out[0], out[1], 1e-13, 1e-13, 1e-13)
+
+
+def _storage_ulp(dev, prec):
+    """Spacing of the storage format at |dev| (normal range)."""
+    import torch
+    dt = {"fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}[prec]
+    t = torch.from_numpy(np.abs(dev)).to(dt)
+    e = torch.frexp(t.float())[1].numpy().astype(np.float64)
+    mant = {"fp32": 23, "fp16": 10, "bf16": 7}[prec]
+    tiny = {"fp32": 2.0 ** -126, "fp16": 2.0 ** -14, "bf16": 2.0 ** -126}[prec]
+    return np.maximum(np.ldexp(1.0, (e - 1 - mant).astype(np.int64)), tiny * 2.0 ** -mant)
+
+
+def _defined_slots(w):
+    """Population slots a step defines, (19 + 7, nz) booleans: every slot
+    except, on a pressure face plane, the f slots fed from beyond the face
+    (unknowns until the next step's outlet fill), and every g of a bounded z
+    face plane (all seven are replaced by the Dirichlet completion of the
+    next step, so a step leaves the slots fed from outside as they were)."""
+    nz = w["nz"]
+    mf = np.ones((19, nz), dtype=bool)
+    mg = np.ones((7, nz), dtype=bool)
+    cz = O.C19[:, 2]
+    if w["faces"][4] == O.PRESSURE:
+        mf[cz > 0, 0] = False
+    if w["faces"][5] == O.PRESSURE:
+        mf[cz < 0, nz - 1] = False
+    if w["faces"][4] != O.PERIODIC:
+        mg[:, 0] = False
+    if w["faces"][5] != O.PERIODIC:
+        mg[:, nz - 1] = False
+    return mf, mg
+
+
+@pytest.mark.parametrize("prec,ty", [("fp32", "16"), ("fp16", "8"), ("fp16", "16"), ("bf16", "8"),
+                                     ("bf16", "16")])
+@pytest.mark.parametrize("name", list(FUSED))
+def test_fused_matches_unfused_narrow_storage(P, name, prec, ty, monkeypatch):
+    """The single-pass kernel (8- or 16-row tiles; 16-bit storage with its
+    shifted tiles) against the general kernels after one step, population by
+    population: the stored deviations differ by at most one storage ulp plus
+    the rounding of float arithmetic on values of the size w_i rho (w_i T for
+    g): the two paths evaluate the same formulas in different orders.  Slots
+    the step leaves undefined (see _defined_slots) are not compared."""
+    monkeypatch.setenv("LBM_FUSED_TY", ty)
+    w = FUSED[name]()
+    pops = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("LBM_FUSED", flag)
+        sim = P.from_workload(w, precision=prec)
+        sim.step(1)
+        pops.append(sim.populations())
+        sim.close()
+    wf = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)[:, None, None, None]
+    w7 = np.array([0.25] + [0.125] * 6)[:, None, None, None]
+    mf, mg = _defined_slots(w)
+    worst = 0.0
+    for lat, (fa, fb), wt, ref, mask, scale in (
+            ("f", (pops[0][0], pops[1][0]), wf, w["rho_ref"], mf, float(np.max(w["rho0"]))),
+            ("g", (pops[0][1], pops[1][1]), w7, w["T_ref"], mg, float(np.max(w["T0"])))):
+        keep = np.broadcast_to(mask[:, :, None, None], fa.shape)
+        da = np.where(keep, fa - wt * ref, 0.0)
+        db = np.where(keep, fb - wt * ref, 0.0)
+        ulp = _storage_ulp(np.maximum(np.abs(da), np.abs(db)), prec)
+        # float arithmetic on values of the size w_i rho (or w_i T), in a
+        # different order on the two paths
+        arith = 64 * 2.0 ** -24 * wt * scale
+        excess = np.abs(da - db) / (ulp + arith)
+        k = np.unravel_index(np.argmax(excess), excess.shape)
+        _log(f"  {lat}: worst {float(excess[k]):.2f} at (i, z, y, x) = {tuple(int(v) for v in k)}: "
+             f"{da[k]:.9e} vs {db[k]:.9e}")
+        worst = max(worst, float(excess[k]))
+    _log(f"{name} {prec} ty={ty}: fused vs unfused worst difference {worst:.2f} of the bound")
+    assert worst <= 1.0
 
 
 def test_fused_xcd_block_mapping_is_bitwise_the_same(P, monkeypatch):
