@@ -112,13 +112,21 @@ typedef struct {
  * T_ref = 0.86 Tc.  Returns LBM_EINVAL if p is NULL. */
 lbm_status lbm_default_params(lbm_params* p, int32_t nx, int32_t ny, int32_t nz);
 
-/* Bytes of device memory a context needs: state_bytes for the two copies of
+/* Bytes of device memory a context needs for the state of the method: the
+ * D3Q19 populations f_i and D3Q7 populations g_i of eqs. (1) and (13) at one
+ * time level plus the next (streaming of eq. (9) writes a second copy).
+ * state_bytes covers the two copies of
  * the populations (2 * 26 * nz * (nx*ny + 64) * element size: each direction
  * plane is padded by 64 elements), scratch_bytes for fields, wall
  * temperature planes and reduction partials.  Validates *p. */
 lbm_status lbm_required_bytes(const lbm_params* p, size_t* state_bytes, size_t* scratch_bytes);
 
-/* Create a context on the current HIP device.  device_buffer: NULL lets the
+/* Create a context for the problem the paper states in Sec. 2-4: the grid
+ * (dx = dt = 1), the Peng-Robinson parameters of eqs. (54)-(55), G of eq.
+ * (6), the relaxation rates of eq. (11) and of the D3Q7 matrix (conductivity
+ * after eq. (33)), c_v and wbar of eqs. (13)-(14), vartheta of eq. (13), and
+ * the face conditions of Sec. 3.
+ * Create it on the current HIP device.  device_buffer: NULL lets the
  * library allocate (and later free) its memory; otherwise a caller-owned
  * device allocation of at least state_bytes + scratch_bytes that must outlive
  * the context.  hip_stream: a hipStream_t, or NULL for the default stream.
@@ -142,7 +150,9 @@ lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_by
  * initial mass for evap_mass.  Synchronous. */
 lbm_status lbm_init(lbm_ctx* ctx, const double* rho, const double* u, const double* T);
 
-/* Replace the Dirichlet temperature of a wall face (4 = -z, 5 = +z) by a
+/* T_b of the thermal Dirichlet condition of Sec. 3.1, eqs. (35)-(36),
+ * g_i(x_b) = w_i T_b + g_i(x_f) - w_i T(x_f), as a field over a wall face:
+ * replace the Dirichlet temperature of a wall face (4 = -z, 5 = +z) by a
  * host FP64 field of nx*ny values (index x + nx*y).  NULL restores the
  * uniform face_T.  Synchronous. */
 lbm_status lbm_set_wall_T(lbm_ctx* ctx, int32_t face, const double* Tw);
@@ -150,7 +160,12 @@ lbm_status lbm_set_wall_T(lbm_ctx* ctx, int32_t face, const double* Tw);
 /* Set kappa_w = tan(pi/2 - theta) of eq. (37). */
 lbm_status lbm_set_kappa(lbm_ctx* ctx, double kappa_w);
 
-/* Advance nsteps >= 0 time steps.  The work is enqueued on the ctx stream;
+/* Advance nsteps >= 0 time steps of the method: per step the boundary
+ * completion of Sec. 3 (eqs. (34)-(53)), rho and T (eqs. (3), (25)), psi
+ * (eqs. (7), (54)), the force (eq. (6)), the velocities (eqs. (4)-(5)), the
+ * source (eqs. (15), (27)-(29)), both collisions (eqs. (8), (10), (11) and
+ * (13)-(14)) and streaming with the rho c_v blend (eqs. (9), (13)).  The
+ * work is enqueued on the ctx stream;
  * the call synchronises once at the end to read the non-physical-state flag
  * and returns LBM_ENONPHYS if any step met rho <= 0, rho*b >= 1, T <= 0,
  * a negative psi radicand or a NaN (the state stays readable). */
@@ -186,8 +201,12 @@ lbm_status lbm_save_bytes(const lbm_ctx* ctx, size_t* bytes);
 lbm_status lbm_save(lbm_ctx* ctx, void* host_dst, size_t bytes);
 lbm_status lbm_load(lbm_ctx* ctx, const void* host_src, size_t bytes);
 
-/* FP64 diagnostics of the current state (mass, energy, liquid volume,
- * evaporated mass), reduced on the GPU in a fixed order.  Synchronous. */
+/* FP64 diagnostics of the current state, reduced on the GPU in a fixed
+ * order: mass sum(rho), energy sum(rho c_v T), liquid volume (the droplet
+ * volume behind the diameter D of the d^2 law, Sec. 4.2, eq. (56)) and the
+ * evaporated mass M(init) - M(now).  Fields with the boundary nodes
+ * completed (rho_out on outlet nodes).  Errors: LBM_EINVAL for NULL
+ * arguments, LBM_ESTATE before lbm_init, LBM_EHIP.  Synchronous. */
 lbm_status lbm_reduce(lbm_ctx* ctx, lbm_diag* out);
 
 /* Discrete adjoint of nsteps time steps from the current state t0.

@@ -13,8 +13,7 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# LBM3D_LIB selects another build of the same library (A/B measurements)
-LIB_PATH = os.environ.get("LBM3D_LIB") or os.path.join(_HERE, "liblbm3d.so")
+LIB_PATH = os.path.join(_HERE, "liblbm3d.so")
 
 FP64, FP32_DEV, FP16_DEV, BF16_DEV = 0, 1, 2, 3
 PERIODIC, WALL, PRESSURE = 0, 1, 2
