@@ -246,6 +246,22 @@ lbm_status lbm_adjoint_bytes(const lbm_ctx* ctx, const lbm_adjoint_spec* spec, s
 lbm_status lbm_adjoint(lbm_ctx* ctx, const lbm_adjoint_spec* spec, double* J, double* dJ_dTw, double* dJ_dkappa,
                        int32_t dst_on_device);
 
+/* lbm_adjoint for callers that cannot allocate device memory (code under HIP
+ * graph capture of the surrounding work, tight serving or optimisation loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * lbm_adjoint, computed by the same kernels, but the workspace (the
+ * lbm_adjoint_bytes of the request) lives in a fixed 64 MiB device array that
+ * the library holds on every GPU it runs on until the process ends; the call
+ * itself allocates and frees nothing.  Requests needing more than 64 MiB
+ * return LBM_ENOMEM before any work (the state stays at t0).  The context's
+ * device must be the current device (LBM_EINVAL otherwise).  Every call on
+ * one GPU shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (two host threads, or contexts on different streams
+ * whose calls interleave) race and must be serialised by the caller.
+ * Synchronous. */
+lbm_status lbm_adjoint_noalloc(lbm_ctx* ctx, const lbm_adjoint_spec* spec, double* J, double* dJ_dTw,
+                               double* dJ_dkappa, int32_t dst_on_device);
+
 /* Message of the last failing call on ctx (or of the last failing
  * lbm_create when ctx is NULL).  Valid until the next call on ctx. */
 const char* lbm_last_error(const lbm_ctx* ctx);

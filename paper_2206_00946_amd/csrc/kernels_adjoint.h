@@ -484,6 +484,13 @@ __global__ void __launch_bounds__(256) k_adj_dirichlet(C* __restrict__ lgo, doub
   }
 }
 
+// v[0 .. n) = 0 (accumulators of the reverse sweep; a kernel rather than a
+// memset, so that the sweep enqueues only kernels and copies)
+__global__ void __launch_bounds__(256) k_zero_f64(double* __restrict__ v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = 0.0;
+}
+
 // Fixed-order sum of n values into *acc (one workgroup).
 template <typename C>
 __global__ void __launch_bounds__(RED_THREADS) k_accumulate(const C* __restrict__ v, long long n,

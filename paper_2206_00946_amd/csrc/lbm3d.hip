@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -21,6 +22,17 @@ using namespace lbm;
 namespace {
 
 std::string g_create_error;
+
+// Workspace of lbm_adjoint_noalloc: one fixed array in device memory, which
+// every GPU the library runs on holds (its own copy) until the process ends.
+// Host code never passes the array's name to a kernel (on the host it only
+// stands for the symbol); the device address of each GPU's copy is looked up
+// once per device with hipGetSymbolAddress and used instead.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 constexpr size_t kAlign = 256;
 constexpr long long kSlab = 1ll << 22;  // cells per host<->device staging slab
@@ -71,6 +83,7 @@ struct lbm_ctx {
   int fused_chunk = 0;  // z planes per workgroup of the fused kernel (0: all)
   int fused_ty = 8;     // tile height of the fused kernel
   bool fused_map = false;  // fused kernel: each XCD a 2 x 4 block of tiles
+  int device = 0;  // HIP device current at lbm_create
   std::string err;
 };
 
@@ -446,9 +459,11 @@ struct DeviceBlock {
   }
 };
 
+// workspace: NULL allocates the plan's workspace for the call (and frees it
+// on return); otherwise ws_bytes of device memory the caller provides.
 template <typename S>
 lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, double* dJ_dTw, double* dJ_dkappa,
-                       int32_t on_device) {
+                       int32_t on_device, void* workspace = nullptr, size_t ws_bytes = 0) {
   using C = typename Storage<S>::C;
   using I = Impl<S>;
   const lbm_params& p = ctx->p;
@@ -458,15 +473,23 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   const long long P = (long long)p.nx * p.ny;
   DeviceBlock blk;
   blk.stream = ctx->stream;
-  {
+  char* b = nullptr;
+  if (workspace) {
+    if (a.total > ws_bytes) {
+      ctx->err = std::string("adjoint workspace of ") + std::to_string(a.total) + " bytes exceeds the " +
+                 std::to_string(ws_bytes) + " bytes available";
+      return LBM_ENOMEM;
+    }
+    b = (char*)workspace;
+  } else {
     const hipError_t e = hipMalloc(&blk.ptr, a.total);
     if (e != hipSuccess) {
       blk.ptr = nullptr;
       ctx->err = std::string("adjoint workspace of ") + std::to_string(a.total) + " bytes: " + hipGetErrorString(e);
       return LBM_ENOMEM;
     }
+    b = (char*)blk.ptr;
   }
-  char* b = (char*)blk.ptr;
   auto ck_f = [&](int k) { return (S*)(b + a.off_ck + (size_t)k * a.state()); };
   auto ck_g = [&](int k) { return (S*)(b + a.off_ck + (size_t)k * a.state() + a.fbytes); };
   auto sg_f = [&](int j) { return (S*)(b + a.off_seg + (size_t)j * a.state()); };
@@ -516,9 +539,10 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   const Phys<C> ph = phys_of<C>(p);
   const unsigned nb = blocks_for(N), npb = blocks_for(P);
   hipLaunchKernelGGL(k_adj_seed<C>, dim3(nb), dim3(256), 0, st, lf[0], lg[0], geo);
-  HIPCHK(ctx, hipMemsetAsync(grad, 0, P * 8, st));
-  HIPCHK(ctx, hipMemsetAsync(acc, 0, 64, st));
-  HIPCHK(ctx, hipMemsetAsync(kap, 0, 2 * P * 8, st));
+  hipLaunchKernelGGL(k_zero_f64, dim3(npb), dim3(256), 0, st, grad, P);
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, st, acc, 8ll);
+  hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(2 * P)), dim3(256), 0, st, kap, 2 * P);
+  HIPCHK(ctx, hipGetLastError());
   int cur = 0;
   for (int k = a.nseg - 1; k >= 0; --k) {
     const int len = std::min(a.L, a.nsteps - k * a.L);
@@ -652,6 +676,7 @@ lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_by
   if (!ctx) { g_create_error = "host allocation failed"; return LBM_ENOMEM; }
   ctx->p = *p;
   ctx->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) ctx->device = -1;
   if (device_buffer) {
     if (buffer_bytes < need || ((uintptr_t)device_buffer % kAlign) != 0) {
       g_create_error = "device_buffer too small or not 256-byte aligned";
@@ -931,6 +956,41 @@ lbm_status lbm_adjoint(lbm_ctx* ctx, const lbm_adjoint_spec* spec, double* J, do
     case LBM_FP32_DEV: return adjoint_run<float>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device);
     case LBM_FP16_DEV: return adjoint_run<_Float16>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device);
     default: return adjoint_run<bf16>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device);
+  }
+}
+
+lbm_status lbm_adjoint_noalloc(lbm_ctx* ctx, const lbm_adjoint_spec* spec, double* J, double* dJ_dTw,
+                               double* dJ_dkappa, int32_t dst_on_device) {
+  if (!ctx) return LBM_EINVAL;
+  const lbm_status s = adjoint_check(ctx, spec, ctx->err);
+  if (s != LBM_OK) return s;
+  if (!ctx->initialised) { ctx->err = "lbm_adjoint_noalloc before lbm_init"; return LBM_ESTATE; }
+  int dev = -1;
+  HIPCHK(ctx, hipGetDevice(&dev));
+  if (dev != ctx->device || dev < 0 || dev >= kMaxDevices) {
+    ctx->err = "lbm_adjoint_noalloc: the context's device is not the current device";
+    return LBM_EINVAL;
+  }
+  void* ws = nullptr;
+  {
+    // the device address of this GPU's copy of the workspace array, looked up
+    // once per device with that device current
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) return hip_fail(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                   "hipGetSymbolAddress(scratch)");
+      g_scratch_ptr[dev] = ptr;
+    }
+    ws = g_scratch_ptr[dev];
+  }
+  switch (ctx->p.precision) {
+    case LBM_FP64: return adjoint_run<double>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device, ws, kNoAllocBytes);
+    case LBM_FP32_DEV: return adjoint_run<float>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device, ws, kNoAllocBytes);
+    case LBM_FP16_DEV:
+      return adjoint_run<_Float16>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device, ws, kNoAllocBytes);
+    default: return adjoint_run<bf16>(ctx, *spec, J, dJ_dTw, dJ_dkappa, dst_on_device, ws, kNoAllocBytes);
   }
 }
 

@@ -56,7 +56,8 @@ class LbmAdjointSpec(ctypes.Structure):
 
 EXPORTS = ["lbm_default_params", "lbm_required_bytes", "lbm_create", "lbm_init", "lbm_set_wall_T",
            "lbm_set_kappa", "lbm_step", "lbm_fields", "lbm_populations", "lbm_save_bytes", "lbm_save",
-           "lbm_load", "lbm_reduce", "lbm_adjoint_bytes", "lbm_adjoint", "lbm_last_error", "lbm_destroy"]
+           "lbm_load", "lbm_reduce", "lbm_adjoint_bytes", "lbm_adjoint", "lbm_adjoint_noalloc", "lbm_last_error",
+           "lbm_destroy"]
 
 _lib = None
 
@@ -90,6 +91,8 @@ def load_library():
     lib.lbm_load.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     lib.lbm_adjoint_bytes.argtypes = [ctypes.c_void_p, P(LbmAdjointSpec), P(ctypes.c_size_t)]
     lib.lbm_adjoint.argtypes = [ctypes.c_void_p, P(LbmAdjointSpec), dp, ctypes.c_void_p, dp, ctypes.c_int32]
+    lib.lbm_adjoint_noalloc.argtypes = [ctypes.c_void_p, P(LbmAdjointSpec), dp, ctypes.c_void_p, dp,
+                                        ctypes.c_int32]
     lib.lbm_last_error.argtypes = [ctypes.c_void_p]
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_destroy.argtypes = [ctypes.c_void_p]
@@ -270,15 +273,17 @@ class Lbm3D:
         self._check(self.lib.lbm_adjoint_bytes(self.ctx, ctypes.byref(spec), ctypes.byref(n)), self.ctx)
         return n.value
 
-    def adjoint(self, nsteps: int, wall_face: int = 4, n_checkpoints: int = 0):
+    def adjoint(self, nsteps: int, wall_face: int = 4, n_checkpoints: int = 0, noalloc: bool = False):
         """Advance nsteps and return (J, dJ/dT_w as (ny, nx), dJ/dkappa_w) for the
-        evaporated mass J = M(t0) - M(t0 + nsteps)."""
+        evaporated mass J = M(t0) - M(t0 + nsteps).  noalloc: use
+        lbm_adjoint_noalloc (workspace in the library's fixed device array)."""
         spec = LbmAdjointSpec(int(nsteps), int(n_checkpoints), 0, int(wall_face))
         J = ctypes.c_double()
         dk = ctypes.c_double()
         grad = np.empty(self.params.nx * self.params.ny)
-        self._check(self.lib.lbm_adjoint(self.ctx, ctypes.byref(spec), ctypes.byref(J), grad.ctypes.data,
-                                         ctypes.byref(dk), 0), self.ctx)
+        fn = self.lib.lbm_adjoint_noalloc if noalloc else self.lib.lbm_adjoint
+        self._check(fn(self.ctx, ctypes.byref(spec), ctypes.byref(J), grad.ctypes.data, ctypes.byref(dk), 0),
+                    self.ctx)
         return J.value, grad.reshape(self.params.ny, self.params.nx), dk.value
 
 
