@@ -178,8 +178,11 @@ __device__ __forceinline__ void st_at(S* plane, unsigned bytes, unsigned voff, u
 
 // OUT: the set-up has a pressure z face.  Closed and periodic set-ups run
 // the instantiation without the outlet code, which keeps that code's scalar
-// registers out of the march.
-template <typename S, int TY, bool OUT>
+// registers out of the march.  RAG: nx is not a multiple of 64 (a last tile
+// column with idle lanes); with whole tiles every lane stores, and the
+// instantiation carries no lane predicate around its stores (the predicate
+// costs the 16-bit steps 8 %).
+template <typename S, int TY, bool OUT, bool RAG>
 __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, const S* __restrict__ gA,
                                                    S* __restrict__ fB, S* __restrict__ gB,
                                                    FusedArgs<typename Storage<S>::C> a) {
@@ -222,8 +225,8 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   // active columns of this tile (all 64 unless nx is ragged); lanes from W on
   // are idle duplicates of the cells that follow
-  const int W = min(TX, nx - x0);
-  const bool act = tx < W;
+  const int W = RAG ? min(TX, nx - x0) : TX;
+  const bool act = !RAG || tx < W;
   const long long PS = a.pitch;  // population planes: direction i of level z starts at (z*Q + i)*PS
   // 16-bit storage: tiles start 2 columns past a 64-column boundary, so that
   // the side halo columns lie in 128-byte lines the tile loads itself (a row
@@ -232,7 +235,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   // than it saves (FP32 +4 %, FP64 +9 %), so those tiles stay aligned.
   constexpr int XS = sizeof(S) == 2 ? 2 : 0;
   x0 += XS;
-  const int x = (x0 + tx) % nx, y = y0 + ty;
+  const int x = RAG ? (x0 + tx) % nx : (XS ? wrapn(x0 + tx, nx) : x0 + tx), y = y0 + ty;
   constexpr unsigned ES = sizeof(S);
   const unsigned col = (unsigned)(x + nx * y);
   const unsigned colb = col * ES;
@@ -771,6 +774,7 @@ inline bool fused_supported(const lbm_params& p, int ty) {
   if (!zper && !zbound) return false;
   if (ty != 8 && (ty != 16 || p.precision == LBM_FP64)) return false;
   if (p.nx < 8 || p.ny % ty != 0) return false;
+  if (p.nx % FTX != 0 && ty != 8) return false;  // ragged nx: 8-row tiles only
   if (p.nz < 4) return false;
   // buffer offsets are 32-bit: the 19 direction planes of one level must span
   // less than the offset that marks a halo lane without a cell (0xFFFFFF00)
@@ -809,7 +813,13 @@ struct FusedImpl {
     a.wall_Tw[0] = Tw0;
     a.wall_Tw[1] = Tw1;
     a.flag = flag;
-    if (a.zpres[0] || a.zpres[1]) return launch<true>(a, TY, nchunks, stream, fA, gA, fB, gB);
+    const bool out = a.zpres[0] || a.zpres[1];
+    if (p.nx % FTX != 0) {
+      // ragged nx: 8-row tiles (the context asks for no other height then)
+      if (out) return launch_rag<true>(a, nchunks, stream, fA, gA, fB, gB);
+      return launch_rag<false>(a, nchunks, stream, fA, gA, fB, gB);
+    }
+    if (out) return launch<true>(a, TY, nchunks, stream, fA, gA, fB, gB);
     return launch<false>(a, TY, nchunks, stream, fA, gA, fB, gB);
   }
   template <bool OUT>
@@ -817,12 +827,20 @@ struct FusedImpl {
                            S* fB, S* gB) {
     if constexpr (sizeof(S) <= 4) {
       if (TY == 16) {
-        hipLaunchKernelGGL((k_fused<S, 16, OUT>), dim3(a.ntiles * nchunks), dim3(FTX * 16), 0, stream, fA, gA, fB,
-                           gB, a);
+        hipLaunchKernelGGL((k_fused<S, 16, OUT, false>), dim3(a.ntiles * nchunks), dim3(FTX * 16), 0, stream, fA,
+                           gA, fB, gB, a);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_fused<S, 8, OUT>), dim3(a.ntiles * nchunks), dim3(FTX * 8), 0, stream, fA, gA, fB, gB, a);
+    hipLaunchKernelGGL((k_fused<S, 8, OUT, false>), dim3(a.ntiles * nchunks), dim3(FTX * 8), 0, stream, fA, gA, fB,
+                       gB, a);
+    return hipGetLastError();
+  }
+  template <bool OUT>
+  static hipError_t launch_rag(const FusedArgs<C>& a, int nchunks, hipStream_t stream, const S* fA, const S* gA,
+                               S* fB, S* gB) {
+    hipLaunchKernelGGL((k_fused<S, 8, OUT, true>), dim3(a.ntiles * nchunks), dim3(FTX * 8), 0, stream, fA, gA, fB,
+                       gB, a);
     return hipGetLastError();
   }
 };

@@ -44,6 +44,7 @@ int main() {
   std::printf("ty16_512x512x384_fp32 %d\n", lbm::fused_supported(box(512, 512, 384, LBM_FP32_DEV, LBM_FACE_WALL), 16));
   std::printf("ty16_512x512x384_fp64 %d\n", lbm::fused_supported(box(512, 512, 384, LBM_FP64, LBM_FACE_WALL), 16));
   std::printf("ty16_64x8x8_fp32 %d\n", lbm::fused_supported(box(64, 8, 8, LBM_FP32_DEV, LBM_FACE_PERIODIC), 16));
+  std::printf("ty16_ragged_96x16x8_fp32 %d\n", lbm::fused_supported(box(96, 16, 8, LBM_FP32_DEV, LBM_FACE_PERIODIC), 16));
   // z planes per workgroup chosen by the context
   std::printf("chunk_512x512x384 %d\n", lbm::fused_chunk_planes(512, 512, 384, 8));
   std::printf("chunk_256x256x256 %d\n", lbm::fused_chunk_planes(256, 256, 256, 8));

@@ -20,6 +20,7 @@ EXPECTED = {
     "plane_4096x4096_fp64": 1, "plane_8192x4096_fp32": 1, "plane_8192x4096_fp64": 0,
     "plane_8192x8192_fp32": 0,
     "ty16_512x512x384_fp32": 1, "ty16_512x512x384_fp64": 0, "ty16_64x8x8_fp32": 0,
+    "ty16_ragged_96x16x8_fp32": 0,
     # z planes per workgroup: one round of 256 workgroups where the tiles
     # allow (256^3: 128 tiles x 2 chunks), whole columns at 512^2 (512 tiles)
     "chunk_512x512x384": 384, "chunk_256x256x256": 128, "chunk_128x128x128": 16,

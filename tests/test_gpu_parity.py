@@ -469,8 +469,9 @@ def test_fused_matches_unfused_narrow_storage(P, name, prec, ty, monkeypatch):
     """The single-pass kernel (8- or 16-row tiles; 16-bit storage with its
     shifted tiles) against the general kernels after one step, population by
     population: the stored deviations differ by at most one storage ulp plus
-    the rounding of float arithmetic on values of the size w_i rho (w_i T for
-    g): the two paths evaluate the same formulas in different orders.  Slots
+    the rounding of float arithmetic on values of the size w_i rho (w_i rho
+    c_v T for g): the two paths evaluate the same formulas in different
+    orders.  Slots
     the step leaves undefined (see _defined_slots) are not compared."""
     monkeypatch.setenv("LBM_FUSED_TY", ty)
     w = FUSED[name]()
@@ -487,12 +488,14 @@ def test_fused_matches_unfused_narrow_storage(P, name, prec, ty, monkeypatch):
     worst = 0.0
     for lat, (fa, fb), wt, ref, mask, scale in (
             ("f", (pops[0][0], pops[1][0]), wf, w["rho_ref"], mf, float(np.max(w["rho0"]))),
-            ("g", (pops[0][1], pops[1][1]), w7, w["T_ref"], mg, float(np.max(w["T0"])))):
+            ("g", (pops[0][1], pops[1][1]), w7, w["T_ref"], mg,
+             float(np.max(w["rho0"]) * (w.get("cv") or 5.0) * np.max(w["T0"])))):
         keep = np.broadcast_to(mask[:, :, None, None], fa.shape)
         da = np.where(keep, fa - wt * ref, 0.0)
         db = np.where(keep, fb - wt * ref, 0.0)
         ulp = _storage_ulp(np.maximum(np.abs(da), np.abs(db)), prec)
-        # float arithmetic on values of the size w_i rho (or w_i T), in a
+        # float arithmetic on values of the size w_i rho (w_i rho c_v T for g,
+        # whose blend and source scale with the energy density), in a
         # different order on the two paths
         arith = 64 * 2.0 ** -24 * wt * scale
         excess = np.abs(da - db) / (ulp + arith)
