@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--adjoint-workload", default="heated_wall_adjoint_96",
                     help="workload of the adjoint timing ('' to skip)")
     ap.add_argument("--adjoint-precisions", default="fp64,fp32")
-    ap.add_argument("--other-workloads", default="heated_wall_256",
+    ap.add_argument("--other-workloads", default="heated_wall_256,droplet_open_128,heated_wall_adjoint_96",
                     help="further workloads timed in FP32 and FP64 storage ('' for none)")
     ap.add_argument("--other-steps", type=int, default=50)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
@@ -118,6 +118,15 @@ def measured_traffic(workload, prec, launches_cells):
     if t.get("kernel_hash") != fused_kernel_hash():
         return None
     return t.get("hbm_bytes_per_launch")
+
+
+def step_kernels(w):
+    """Which kernels run a step of the workload: the single-pass kernel takes
+    x/y-periodic set-ups (any z faces, vartheta = 0); outlets on x or y faces
+    run the general kernels (three launches)."""
+    if all(f == 0 for f in w["faces"][:4]) and not w.get("theta_corr"):
+        return "single-pass"
+    return "general (three kernels)"
 
 
 def time_precision(P, torch, w, prec, steps, warmup):
@@ -305,7 +314,7 @@ def main():
     others = {}
     for name in [v for v in args.other_workloads.split(",") if v and v != args.workload]:
         wo = synth.named(name)
-        others[name] = {"grid": [wo["nx"], wo["ny"], wo["nz"]], "faces": wo["faces"]}
+        others[name] = {"grid": [wo["nx"], wo["ny"], wo["nz"]], "faces": wo["faces"], "kernels": step_kernels(wo)}
         for prec in ("fp32", "fp64"):
             print(f"[bench] {name} {prec}: {args.other_steps} steps", file=sys.stderr, flush=True)
             r = time_precision(P, torch, wo, prec, args.other_steps, 5)
@@ -316,7 +325,8 @@ def main():
     if args.adjoint_workload:
         wa = synth.named(args.adjoint_workload)
         adjoint = {"workload": args.adjoint_workload, "grid": [wa["nx"], wa["ny"], wa["nz"]], "steps": wa["steps"],
-                   "objective": "evaporated mass M(0)-M(N)", "checkpoints": "ceil(sqrt(N))"}
+                   "objective": "evaporated mass M(0)-M(N)", "checkpoints": "ceil(sqrt(N))",
+                   "forward_kernels": step_kernels(wa)}
         for prec in [v for v in args.adjoint_precisions.split(",") if v]:
             print(f"[bench] adjoint {prec} on {args.adjoint_workload}", file=sys.stderr, flush=True)
             adjoint[prec] = time_adjoint(P, torch, wa, prec)

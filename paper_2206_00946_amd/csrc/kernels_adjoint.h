@@ -16,6 +16,15 @@
 // give the adjoint of s_t and add the step's contribution to dJ/dT_w and
 // dJ/dkappa_w.  Adjoints are held in the compute type C in the population
 // layout of the state; gradients accumulate in FP64.
+//
+// Deferred moment update.  The reverse of S1 (rho = sum f, T = sum g) adds
+// the same rho-adjoint rb and momentum adjoint jb to every f_i (as rb +
+// c_i . jb) and the T-adjoint Tb to every g_i of a cell.  k_adj_psi stores
+// those five values per cell, d = (rb, jb_x, jb_y, jb_z, Tb), instead of
+// reading and rewriting the 26 adjoint populations, and the adjoint of s_t
+// is the pair (l~, d): lf_i = l~f_i + rb + c_i . jb, lg_i = l~g_i + Tb.
+// k_adj_collide of the next reverse step adds d where it gathers, and
+// k_adj_dirichlet where it reads the face planes.
 #pragma once
 
 #include "adjoint.h"
@@ -76,7 +85,8 @@ __device__ __forceinline__ C varpi(int i) {
 
 // adjoint state at t = N of J = M(0) - M(N): dJ/df_i = -1 where rho = sum f
 template <typename C>
-__global__ void __launch_bounds__(256) k_adj_seed(C* __restrict__ lf, C* __restrict__ lg, Geom g) {
+__global__ void __launch_bounds__(256) k_adj_seed(C* __restrict__ lf, C* __restrict__ lg, C* __restrict__ d,
+                                                  Geom g) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.N) return;
   const int x = (int)(c % g.nx);
@@ -88,6 +98,8 @@ __global__ void __launch_bounds__(256) k_adj_seed(C* __restrict__ lf, C* __restr
   for (int i = 0; i < 19; ++i) lf[pidx(g, 19, i, x, y, z)] = v;
 #pragma unroll
   for (int i = 0; i < 7; ++i) lg[pidx(g, 7, i, x, y, z)] = C(0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) d[c + k * g.N] = C(0);
 }
 
 // div u of a state from its stored real velocity, with the step's own
@@ -110,7 +122,7 @@ __global__ void __launch_bounds__(256) k_div(const C* __restrict__ ureal, C* __r
 template <typename S>
 __global__ void __launch_bounds__(256)
     k_adj_collide(const typename Storage<S>::C* __restrict__ lfi, const typename Storage<S>::C* __restrict__ lgi,
-                  const S* __restrict__ gA, const S* __restrict__ gnext,
+                  const typename Storage<S>::C* __restrict__ di, const S* __restrict__ gA, const S* __restrict__ gnext,
                   const typename Storage<S>::C* __restrict__ rho_f, const typename Storage<S>::C* __restrict__ T_f,
                   const typename Storage<S>::C* __restrict__ ueq, const typename Storage<S>::C* __restrict__ du,
                   const typename Storage<S>::C* __restrict__ divf,
@@ -136,14 +148,25 @@ __global__ void __launch_bounds__(256)
   const bool* zin = nb.zin;
   const int* zl = nb.zl;
 
+  // adjoint of f_i, g_i of s_{t+1} at column cl, level zz: the stored part
+  // plus the deferred moment update of that cell
+  // (only the momentum components along c_i are read)
+  auto lf_at = [&](int i, int zz, int cl) -> C {
+    const long long cc = nb.cell(zz, cl);
+    C v = lfi[pop(19, i, zz, cl)] + di[cc];
+    if (CX[i]) v += C(CX[i]) * di[cc + N];
+    if (CY[i]) v += C(CY[i]) * di[cc + 2 * N];
+    if (CZ[i]) v += C(CZ[i]) * di[cc + 3 * N];
+    return v;
+  };
   // S9: f*_i(x) went to slot i at x + c_i, to slot opp(i) at x (wall), or
   // left the domain (outlet)
   C fsb[19];
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const int d = CZ[i] + 1;
-    if (zin[d]) fsb[i] = lfi[pop(19, i, zl[d], ncol(i))];
-    else if (g.face[CZ[i] < 0 ? 4 : 5] == FACE_WALL) fsb[i] = lfi[pop(19, opp19(i), z, col)];
+    if (zin[d]) fsb[i] = lf_at(i, zl[d], ncol(i));
+    else if (g.face[CZ[i] < 0 ? 4 : 5] == FACE_WALL) fsb[i] = lf_at(opp19(i), z, col);
     else fsb[i] = C(0);
   }
   // S10: g*_i(x) enters the blend at y = x + c_i with weight 1/(rho(y) c_v)
@@ -154,7 +177,7 @@ __global__ void __launch_bounds__(256)
     gsb[i] = C(0);
     if (zin[d]) {
       const long long cd = nb.cell(zl[d], ncol(i));
-      gsb[i] = lgi[pop(7, i, zl[d], ncol(i))] / (rho_f[cd] * ph.cv);
+      gsb[i] = (lgi[pop(7, i, zl[d], ncol(i))] + di[cd + 4 * N]) / (rho_f[cd] * ph.cv);
     }
   }
   C fb[19], gb[7];
@@ -192,7 +215,7 @@ __global__ void __launch_bounds__(256)
   const C inv = C(1) / (rho * ph.cv);
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
-    const C l = lgi[pop(7, i, z, col)];
+    const C l = lgi[pop(7, i, z, col)] + di[c + 4 * N];
     if (zin[1 - CZ[i]]) {
       gb[i] += l * (C(1) - inv);
       if (n.count == 0) {
@@ -378,10 +401,10 @@ __global__ void __launch_bounds__(256) k_adj_ghost(const C* __restrict__ Fb, con
 
 // Reverse of S3 (force stencil, with every ghost rule), S2 (psi) and S1
 // (rho = sum f, T = sum g).  Completes the adjoint of the completed f and g
-// of s_t (lfo, lgo).
+// of s_t by its deferred moment update d (rb, jb, Tb per cell).
 template <typename C>
 __global__ void __launch_bounds__(256)
-    k_adj_psi(C* __restrict__ lfo, C* __restrict__ lgo, const C* __restrict__ a_rho, const C* __restrict__ a_T,
+    k_adj_psi(C* __restrict__ dO, const C* __restrict__ a_rho, const C* __restrict__ a_T,
               const C* __restrict__ jb_f, const C* __restrict__ Fb, const C* __restrict__ psi,
               const C* __restrict__ rho_f, const C* __restrict__ T_f, const C* __restrict__ gadj,
               const C* __restrict__ ax, const C* __restrict__ ay, Geom g, Phys<C> ph) {
@@ -440,25 +463,24 @@ __global__ void __launch_bounds__(256)
   pr_partials(rho, T, ph, dp_dr, dpdT, dpdT_dr, dpdT_dT);
   const C q = ps > C(0) ? pb / (ph.G * ps) : C(0);
   const C Tb = a_T[c] + q * dpdT;
-  if (!n.pressure) {
-    const C rb = a_rho[c] + q * (dp_dr - C(1) / C(3));
-    const C jx = jb_f[c], jy = jb_f[c + N], jz = jb_f[c + 2 * N];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const long long k = nb.pop(19, i, z, nb.col);
-      lfo[k] += rb + C(CX[i]) * jx + C(CY[i]) * jy + C(CZ[i]) * jz;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 7; ++i) lgo[nb.pop(7, i, z, nb.col)] += Tb;
+  // on outlet nodes rho is fixed and the known populations took their
+  // adjoint in k_adj_outlet
+  const bool inner = !n.pressure;
+  dO[c] = inner ? a_rho[c] + q * (dp_dr - C(1) / C(3)) : C(0);
+  dO[c + N] = inner ? jb_f[c] : C(0);
+  dO[c + 2 * N] = inner ? jb_f[c + N] : C(0);
+  dO[c + 3 * N] = inner ? jb_f[c + 2 * N] : C(0);
+  dO[c + 4 * N] = Tb;
 }
 
 // Reverse of S0 on the z faces, one thread per (x, y): g_i(x_b) = w_i T_b +
 // g_i(x_f) - w_i sum_j g_j(x_f).  Adds sum_i w_i gb_i(x_b) to dJ/dT_b of the
-// selected face and clears the adjoint of the overwritten g(x_b).
+// selected face and clears the adjoint of the overwritten g(x_b) (its
+// stored part and its deferred Tb).
 template <typename C>
-__global__ void __launch_bounds__(256) k_adj_dirichlet(C* __restrict__ lgo, double* __restrict__ grad_Tw,
-                                                       int grad_face, Geom g, Phys<C> ph) {
+__global__ void __launch_bounds__(256) k_adj_dirichlet(C* __restrict__ lgo, C* __restrict__ dO,
+                                                       double* __restrict__ grad_Tw, int grad_face, Geom g,
+                                                       Phys<C> ph) {
   const long long P = (long long)g.nx * g.ny;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P) return;
@@ -470,11 +492,14 @@ __global__ void __launch_bounds__(256) k_adj_dirichlet(C* __restrict__ lgo, doub
     const int zf = s ? g.nz - 2 : 1;
     C l[7];
     C S = C(0);
+    const long long cb = cell_index(g, x, y, zb);
+    const C Tbd = dO[cb + 4 * g.N];
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
-      l[i] = lgo[pidx(g, 7, i, x, y, zb)];
+      l[i] = lgo[pidx(g, 7, i, x, y, zb)] + Tbd;
       S += (i == 0 ? ph.w0 : ph.w1) * l[i];
     }
+    dO[cb + 4 * g.N] = C(0);
     if (k == grad_face) grad_Tw[t] += (double)S;
 #pragma unroll
     for (int i = 0; i < 7; ++i) {

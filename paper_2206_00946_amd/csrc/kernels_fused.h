@@ -55,6 +55,15 @@ constexpr int kEarlyF = 10;
 template <typename S>
 constexpr int store_cache_policy() { return sizeof(S) == 8 ? 2 : 0; }
 
+// Optional per-cell outputs of a step (the adjoint's recomputation keeps
+// them for the reverse sweep): rho, T, psi (S1-S2), u_eq, du = F/rho and the
+// real velocity (S5, 3 components each, component planes of N cells), div u
+// (S6), all of the state the step starts from, flat index x + nx (y + ny z).
+template <typename C>
+struct FusedFields {
+  C *rho, *T, *psi, *ueq, *du, *ureal, *div;
+};
+
 template <typename C>
 struct FusedArgs {
   Phys<C> ph;
@@ -68,6 +77,8 @@ struct FusedArgs {
   C wall_T[2];            // Dirichlet temperatures of the z = 0 and z = nz - 1 faces
   const double* wall_Tw[2];  // optional per-cell face temperature fields (nx*ny)
   int* flag;
+  FusedFields<C> fo;  // written by the FLD instantiation only
+  void* g_face;       // FLD: the start state's g, whose bounded-face planes get the Dirichlet completion
 };
 
 template <int TY>
@@ -181,8 +192,13 @@ __device__ __forceinline__ void st_at(S* plane, unsigned bytes, unsigned voff, u
 // registers out of the march.  RAG: nx is not a multiple of 64 (a last tile
 // column with idle lanes); with whole tiles every lane stores, and the
 // instantiation carries no lane predicate around its stores (the predicate
-// costs the 16-bit steps 8 %).
-template <typename S, int TY, bool OUT, bool RAG>
+// costs the 16-bit steps 8 %).  FLD: also write the fields of the start
+// state (FusedFields) and its Dirichlet-completed face-plane g, as the
+// general kernels' prepass leaves them (adjoint recomputation, 8-row
+// tiles).  A face-plane g may be rewritten while a neighbouring tile loads
+// it as halo: that tile replaces the loaded value by the same completion,
+// which reads only the plane inside.
+template <typename S, int TY, bool OUT, bool RAG, bool FLD = false>
 __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, const S* __restrict__ gA,
                                                    S* __restrict__ fB, S* __restrict__ gB,
                                                    FusedArgs<typename Storage<S>::C> a) {
@@ -432,6 +448,19 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       const C rad = psi_radicand(rho_c, T, ph);
       if (nonphysical(rho_c, T, rad, ph)) a.flag[0] = 1;
       s_psi[s3][e_own] = fsqrt(rad);
+      if constexpr (FLD) {
+        if (act && p >= z0 && p < z1) {
+          const long long cidx = (long long)zp * nx * ny + col;
+          a.fo.rho[cidx] = rho_c;
+          a.fo.T[cidx] = T;
+          a.fo.psi[cidx] = fsqrt(rad);
+          if (face_plane) {
+            S* gw = (S*)a.g_face + PS * 7 * zp;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) st_at(gw, G7, colb, i * PB, gc[i]);
+          }
+        }
+      }
       s_rho[s4][e_own] = rho_c;
       if (pres_plane) {
         s_ueq[s2][0][e_own] = C(0);
@@ -550,6 +579,19 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         ub[0] = uex + C(0.5) * dux;
         ub[1] = uey + C(0.5) * duy;
         ub[2] = uez + C(0.5) * duz;
+        if constexpr (FLD) {
+          if (act && q >= z0 && q < z1) {
+            const long long NC = (long long)nx * ny * nz;
+            const long long cidx = (long long)zq * nx * ny + col;
+            const C ue[3] = {uex, uey, uez}, dd[3] = {dux, duy, duz};
+#pragma unroll
+            for (int c3 = 0; c3 < 3; ++c3) {
+              a.fo.ueq[cidx + c3 * NC] = ue[c3];
+              a.fo.du[cidx + c3 * NC] = dd[c3];
+              a.fo.ureal[cidx + c3 * NC] = ub[c3];
+            }
+          }
+        }
         s_u[0][e_own] = ub[0];
         s_u[1][e_own] = ub[1];
         s_u[2][e_own] = ub[2];
@@ -652,6 +694,9 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       C gx, gy, gz;
       local_gradT(ga, vf, ph, gx, gy, gz);
       const C Fbar = rho * ph.cv * (ua[0] * gx + ua[1] * gy + ua[2] * gz) + T * pr_dpdT(rho, T, ph) * d0;
+      if constexpr (FLD) {
+        if (act) a.fo.div[(long long)zr * nx * ny + col] = d0;
+      }
       const C og0 = ga[0];
       collide7(ga, Fbar, vf, ph);
       if (act) st_at(gB + PS * 7 * zr, G7, colb, 0u, og0 + (ga[0] - og0) * (inv_cv * rcp(rho)));
@@ -788,9 +833,12 @@ struct FusedImpl {
   using C = typename Storage<S>::C;
   // ty: tile height (8, or 16 for 32/16-bit storage); chunk_planes: z planes
   // per workgroup (0: all); xcd_map: give each XCD a 2 x 4 block of tiles
+  // fo: NULL for a plain step; otherwise the step also writes the fields of
+  // its start state there and completes the start state's face-plane g in
+  // place (8-row tiles)
   static hipError_t step(const lbm_params& p, const Phys<C>& ph, hipStream_t stream, const S* fA, const S* gA, S* fB,
                          S* gB, const double* Tw0, const double* Tw1, int* flag, int ty, int chunk_planes,
-                         bool xcd_map) {
+                         bool xcd_map, const FusedFields<C>* fo = nullptr) {
     FusedArgs<C> a;
     a.ph = ph;
     a.nx = p.nx;
@@ -813,7 +861,24 @@ struct FusedImpl {
     a.wall_Tw[0] = Tw0;
     a.wall_Tw[1] = Tw1;
     a.flag = flag;
+    a.fo = fo ? *fo : FusedFields<C>{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    a.g_face = const_cast<S*>(gA);
     const bool out = a.zpres[0] || a.zpres[1];
+    if (fo) {
+      // the same instantiation as the plain step of this grid, plus the
+      // field stores (the stores only read values the step computes anyway,
+      // so the state it produces is the plain step's)
+      if (TY != 8) return hipErrorInvalidValue;
+      const dim3 grid(a.ntiles * nchunks), block(FTX * 8);
+      if (p.nx % FTX != 0) {
+        if (out) hipLaunchKernelGGL((k_fused<S, 8, true, true, true>), grid, block, 0, stream, fA, gA, fB, gB, a);
+        else hipLaunchKernelGGL((k_fused<S, 8, false, true, true>), grid, block, 0, stream, fA, gA, fB, gB, a);
+      } else {
+        if (out) hipLaunchKernelGGL((k_fused<S, 8, true, false, true>), grid, block, 0, stream, fA, gA, fB, gB, a);
+        else hipLaunchKernelGGL((k_fused<S, 8, false, false, true>), grid, block, 0, stream, fA, gA, fB, gB, a);
+      }
+      return hipGetLastError();
+    }
     if (p.nx % FTX != 0) {
       // ragged nx: 8-row tiles (the context asks for no other height then)
       if (out) return launch_rag<true>(a, nchunks, stream, fA, gA, fB, gB);

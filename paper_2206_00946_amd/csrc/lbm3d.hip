@@ -301,6 +301,17 @@ struct Impl {
                               ctx->fused_map);
   }
 
+  // A single-pass step that also writes the fields of its start state into F
+  // and completes the start state's face-plane g in place (what the prepass
+  // leaves); the adjoint's recomputation on set-ups the single-pass kernel
+  // takes.
+  static hipError_t step_fused_fields(lbm_ctx* ctx, const S* fs, S* gs, S* fd, S* gd, const FieldSet& F) {
+    const lbm_params& p = ctx->p;
+    const FusedFields<C> fo{(C*)F.rho, (C*)F.T, (C*)F.psi, (C*)F.ueq, (C*)F.du, (C*)F.ureal, (C*)F.div};
+    return FusedImpl<S>::step(p, phys_of<C>(p), ctx->stream, fs, gs, fd, gd, ctx->has_Tw[0] ? ctx->Tw[0] : nullptr,
+                              ctx->has_Tw[1] ? ctx->Tw[1] : nullptr, ctx->flag, 8, ctx->fused_chunk, false, &fo);
+  }
+
   static hipError_t step_from(lbm_ctx* ctx, S* fs, S* gs, S* fd, S* gd) {
     return ctx->fused_ok ? step_fused(ctx, fs, gs, fd, gd) : step_ref(ctx, fs, gs, fd, gd);
   }
@@ -375,13 +386,16 @@ lbm_status reduce_now(lbm_ctx* ctx, double out[RED_VALUES]) {
 struct AdjPlan {
   int nsteps = 0, nseg = 0, L = 0;
   size_t fbytes = 0, gbytes = 0;
-  size_t off_ck = 0, off_seg = 0, off_lf[2] = {0, 0}, off_lg[2] = {0, 0}, off_rho = 0, off_T = 0, off_div = 0,
+  size_t off_ck = 0, off_seg = 0, off_lf[2] = {0, 0}, off_lg[2] = {0, 0}, off_d[2] = {0, 0}, off_rho = 0, off_T = 0,
+         off_div = 0,
          off_ueq = 0, off_du = 0, off_gadj = 0, off_ax = 0, off_ay = 0, off_kap = 0, off_grad = 0, off_acc = 0,
          off_fdiv = 0;
-  // fields of every state of a segment, kept from its recomputation (unfused
-  // steps only; the fused kernel writes no fields)
-  bool cache = false;
-  size_t off_fields = 0, fslot = 0, fN = 0;
+  // fields of every state of a segment, kept from its recomputation; with
+  // the single-pass kernel (fused) the step from a segment's last state is
+  // taken once more into a spare state (off_spare) to write that state's
+  // fields, so that every state's fields come from the same kernel
+  bool cache = false, fused = false;
+  size_t off_fields = 0, fslot = 0, fN = 0, off_spare = 0;
   size_t total = 0;
   size_t state() const { return fbytes + gbytes; }
   FieldSet fields(char* base, int j) const {
@@ -390,7 +404,7 @@ struct AdjPlan {
   }
 };
 
-AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp, bool cache_fields) {
+AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp, bool fused) {
   AdjPlan a;
   a.nsteps = sp.nsteps;
   int K = sp.n_checkpoints > 0 ? sp.n_checkpoints : (int)std::ceil(std::sqrt((double)sp.nsteps));
@@ -409,6 +423,7 @@ AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp, bool cache
   for (int k = 0; k < 2; ++k) {
     a.off_lf[k] = o; o = align_up(o + 19 * NP * cs);
     a.off_lg[k] = o; o = align_up(o + 7 * NP * cs);
+    a.off_d[k] = o; o = align_up(o + 5 * N * cs);  // deferred moment update (rb, jb, Tb) per cell
   }
   a.off_rho = o; o = align_up(o + N * cs);
   a.off_T = o; o = align_up(o + N * cs);
@@ -422,11 +437,13 @@ AdjPlan adjoint_plan(const lbm_params& p, const lbm_adjoint_spec& sp, bool cache
   a.off_grad = o; o = align_up(o + P * 8);
   a.off_acc = o; o = align_up(o + 64);
   a.off_fdiv = o; o = align_up(o + N * cs);  // div u of the state when the fields are not stored
-  a.cache = cache_fields;
-  if (a.cache) {
-    a.fN = N * cs;
-    a.fslot = align_up(13 * a.fN);
-    a.off_fields = o; o += (size_t)a.L * a.fslot;
+  a.cache = true;
+  a.fused = fused;
+  a.fN = N * cs;
+  a.fslot = align_up(13 * a.fN);
+  a.off_fields = o; o += (size_t)a.L * a.fslot;
+  if (a.fused) {
+    a.off_spare = o; o += a.state();
   }
   a.total = o;
   return a;
@@ -467,7 +484,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   using C = typename Storage<S>::C;
   using I = Impl<S>;
   const lbm_params& p = ctx->p;
-  const AdjPlan a = adjoint_plan(p, sp, !ctx->fused_ok);
+  const AdjPlan a = adjoint_plan(p, sp, ctx->fused_ok);
   const Geom geo = geom_of(p);
   const long long N = geo.N;
   const long long P = (long long)p.nx * p.ny;
@@ -496,6 +513,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   auto sg_g = [&](int j) { return (S*)(b + a.off_seg + (size_t)j * a.state() + a.fbytes); };
   C* lf[2] = {(C*)(b + a.off_lf[0]), (C*)(b + a.off_lf[1])};
   C* lg[2] = {(C*)(b + a.off_lg[0]), (C*)(b + a.off_lg[1])};
+  C* ld[2] = {(C*)(b + a.off_d[0]), (C*)(b + a.off_d[1])};
   C* a_rho = (C*)(b + a.off_rho);
   C* a_T = (C*)(b + a.off_T);
   C* a_div = (C*)(b + a.off_div);
@@ -538,7 +556,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
   // reverse sweep, one segment at a time
   const Phys<C> ph = phys_of<C>(p);
   const unsigned nb = blocks_for(N), npb = blocks_for(P);
-  hipLaunchKernelGGL(k_adj_seed<C>, dim3(nb), dim3(256), 0, st, lf[0], lg[0], geo);
+  hipLaunchKernelGGL(k_adj_seed<C>, dim3(nb), dim3(256), 0, st, lf[0], lg[0], ld[0], geo);
   hipLaunchKernelGGL(k_zero_f64, dim3(npb), dim3(256), 0, st, grad, P);
   hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, st, acc, 8ll);
   hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(2 * P)), dim3(256), 0, st, kap, 2 * P);
@@ -548,20 +566,27 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
     const int len = std::min(a.L, a.nsteps - k * a.L);
     HIPCHK(ctx, hipMemcpyAsync(sg_f(0), ck_f(k), fsz, hipMemcpyDeviceToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(sg_g(0), ck_g(k), gsz, hipMemcpyDeviceToDevice, st));
-    // recompute the segment; unfused steps keep the fields of every state
+    // recompute the segment, keeping the fields of every state
     for (int j = 1; j < len; ++j) {
-      if (a.cache) HIPCHK(ctx, I::step_ref_to(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j), a.fields(b, j - 1)));
-      else HIPCHK(ctx, I::step_from(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j)));
+      if (a.fused)
+        HIPCHK(ctx, I::step_fused_fields(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j), a.fields(b, j - 1)));
+      else HIPCHK(ctx, I::step_ref_to(ctx, sg_f(j - 1), sg_g(j - 1), sg_f(j), sg_g(j), a.fields(b, j - 1)));
     }
     for (int j = len - 1; j >= 0; --j) {
       const S* gnext = j + 1 < len ? sg_g(j + 1) : (k + 1 < a.nseg ? ck_g(k + 1) : (const S*)ctx->gA);
       FieldSet F = a.cache ? a.fields(b, j) : ctx_fields(ctx);
       if (!F.div) F.div = b + a.off_fdiv;
-      if (!a.cache || j == len - 1) {
-        // fields of a state no recomputed step has written: S0-S5, then div u
-        // with the step's own definition
-        HIPCHK(ctx, I::prepass_to(ctx, sg_f(j), sg_g(j), F));
-        hipLaunchKernelGGL(k_div<C>, dim3(nb), dim3(256), 0, st, (const C*)F.ureal, (C*)F.div, geo);
+      if (j == len - 1) {
+        // fields of a state no recomputed step has written
+        if (a.fused) {
+          // its step once more, into the spare state
+          HIPCHK(ctx, I::step_fused_fields(ctx, sg_f(j), sg_g(j), (S*)(b + a.off_spare),
+                                           (S*)(b + a.off_spare + a.fbytes), F));
+        } else {
+          // S0-S5, then div u with the step's own definition
+          HIPCHK(ctx, I::prepass_to(ctx, sg_f(j), sg_g(j), F));
+          hipLaunchKernelGGL(k_div<C>, dim3(nb), dim3(256), 0, st, (const C*)F.ureal, (C*)F.div, geo);
+        }
       }
       const C* rho = (const C*)F.rho;
       const C* T = (const C*)F.T;
@@ -570,7 +595,7 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
       const C* du = (const C*)F.du;
       const int nx = 1 - cur;
       hipLaunchKernelGGL(k_adj_collide<S>, dim3(nb), dim3(256), 0, st, (const C*)lf[cur], (const C*)lg[cur],
-                         (const S*)sg_g(j), gnext, rho, T, ueq, du, (const C*)F.div, lf[nx], lg[nx], a_rho, a_T,
+                         (const C*)ld[cur], (const S*)sg_g(j), gnext, rho, T, ueq, du, (const C*)F.div, lf[nx], lg[nx], a_rho, a_T,
                          a_ueq, a_du, a_div, geo, ph);
       hipLaunchKernelGGL(k_adj_velocity<C>, dim3(nb), dim3(256), 0, st, (const C*)a_div, a_ueq, a_du,
                          a_rho, rho, ueq, du, geo);
@@ -578,10 +603,11 @@ lbm_status adjoint_run(lbm_ctx* ctx, const lbm_adjoint_spec& sp, double* J, doub
       if (walls)
         hipLaunchKernelGGL(k_adj_ghost<C>, dim3(npb), dim3(256), 0, st, (const C*)a_du, psi, gadj, ax, ay, kap, geo,
                            ph);
-      hipLaunchKernelGGL(k_adj_psi<C>, dim3(nb), dim3(256), 0, st, lf[nx], lg[nx], (const C*)a_rho,
+      hipLaunchKernelGGL(k_adj_psi<C>, dim3(nb), dim3(256), 0, st, ld[nx], (const C*)a_rho,
                          (const C*)a_T, (const C*)a_ueq, (const C*)a_du, psi, rho, T, (const C*)gadj, (const C*)ax,
                          (const C*)ay, geo, ph);
-      hipLaunchKernelGGL(k_adj_dirichlet<C>, dim3(npb), dim3(256), 0, st, lg[nx], grad, (int)sp.wall_face, geo, ph);
+      hipLaunchKernelGGL(k_adj_dirichlet<C>, dim3(npb), dim3(256), 0, st, lg[nx], ld[nx], grad, (int)sp.wall_face,
+                         geo, ph);
       HIPCHK(ctx, hipGetLastError());
       cur = nx;
     }
@@ -941,7 +967,7 @@ lbm_status lbm_adjoint_bytes(const lbm_ctx* ctx, const lbm_adjoint_spec* spec, s
   std::string msg;
   const lbm_status s = adjoint_check(ctx, spec, msg);
   if (s != LBM_OK) return s;
-  *bytes = adjoint_plan(ctx->p, *spec, !ctx->fused_ok).total;
+  *bytes = adjoint_plan(ctx->p, *spec, ctx->fused_ok).total;
   return LBM_OK;
 }
 

@@ -132,12 +132,25 @@ def test_adjoint_matches_complex_step_fp64(P, name):
 
 @pytest.mark.parametrize("name", ["heated_wall_kappa", "fused_heated_wall_kappa"])
 def test_checkpoint_count_does_not_change_the_gradient(P, name):
+    """On the general kernels every state of the reverse sweep is produced and
+    evaluated by the same kernels whatever the segmentation: the gradient is
+    bitwise independent of the checkpoint count.  On the single-pass kernel
+    the recomputed states come from its field-writing instantiation and the
+    checkpoints from the plain one, which agree to rounding: 1e-13."""
     w = _case(name)
     out = [_gpu_adjoint(P, w, n_checkpoints=k) for k in (1, 2, 0, NSTEPS)]
+    # the same request twice: bitwise the same (deterministic)
+    again = _gpu_adjoint(P, w, n_checkpoints=2)
+    assert np.array_equal(again[1], out[1][1]) and again[2] == out[1][2]
     for J, grad, dk, _ in out[1:]:
         assert J == out[0][0]
-        assert np.array_equal(grad, out[0][1])
-        assert dk == out[0][2]
+        if name.startswith("fused_"):
+            eg = float(np.max(np.abs(grad - out[0][1])) / np.max(np.abs(out[0][1])))
+            _log(f"{name}: checkpoint counts differ by {eg:.2e} (dJ/dTw), {abs(dk - out[0][2]) / abs(dk):.2e} (kappa)")
+            assert eg < 1e-13 and abs(dk - out[0][2]) < 1e-13 * abs(dk)
+        else:
+            assert np.array_equal(grad, out[0][1])
+            assert dk == out[0][2]
 
 
 # bounds on the normwise dJ/dT_w and the dJ/dkappa_w differences to FP64
