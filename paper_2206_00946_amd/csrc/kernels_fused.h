@@ -198,7 +198,22 @@ __device__ __forceinline__ void st_at(S* plane, unsigned bytes, unsigned voff, u
 // tiles).  A face-plane g may be rewritten while a neighbouring tile loads
 // it as halo: that tile replaces the loaded value by the same completion,
 // which reads only the plane inside.
-template <typename S, int TY, bool OUT, bool RAG, bool FLD = false>
+// XP: x-deferred streaming between the steps of one multi-step call (whole
+// 8-row tiles).  A D3Q19 population f*_i(x, y, z) may be stored at
+// (x, y + c_iy, z + c_iz), streamed in y and z only; the step that reads
+// such a state takes direction i of cell x from column x - c_ix, which
+// finishes the streaming (eq. (9)) at load time.  Every wave then stores
+// whole rows in place of rows shifted by one cell, which touch one more
+// cache line each, and the shifted loads fall in the lines the side halo
+// brings in anyway.  Bit 0: the input is such a state; bit 1: the output is
+// (the first step of a call reads, and its last step writes, the ordinary
+// post-streaming state).  The D3Q7 populations are streamed as always.
+// Used for FP64 storage, whose non-temporal stores of shifted rows write
+// partial lines (512 x 512 x 384: 10.6 -> 9.8 ms per step); with 4- and
+// 2-byte storage the shifted loads add as many line requests as the stores
+// save (FP32 4.94 -> 5.04 ms, FP16 3.96 -> 4.29 ms), and those steps store
+// shifted rows.
+template <typename S, int TY, bool OUT, bool RAG, bool FLD = false, int XP = 0>
 __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, const S* __restrict__ gA,
                                                    S* __restrict__ fB, S* __restrict__ gB,
                                                    FusedArgs<typename Storage<S>::C> a) {
@@ -248,8 +263,11 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   // the side halo columns lie in 128-byte lines the tile loads itself (a row
   // of 64 cells then spans two lines instead of one): FP16 / BF16 steps 3 %
   // shorter.  With 4- and 8-byte storage the extra line per row costs more
-  // than it saves (FP32 +4 %, FP64 +9 %), so those tiles stay aligned.
-  constexpr int XS = sizeof(S) == 2 ? 2 : 0;
+  // than it saves (FP32 +4 %, FP64 +9 %), so those tiles stay aligned, and so
+  // do the tiles of x-deferred steps, whose rows are stored in place.
+  constexpr bool INP = (XP & 1) != 0, OUTP = (XP & 2) != 0;
+  static_assert(XP == 0 || (TY == 8 && !RAG && !FLD), "x-deferred streaming: whole 8-row tiles only");
+  constexpr int XS = sizeof(S) == 2 && XP == 0 ? 2 : 0;
   x0 += XS;
   const int x = RAG ? (x0 + tx) % nx : (XS ? wrapn(x0 + tx, nx) : x0 + tx), y = y0 + ty;
   constexpr unsigned ES = sizeof(S);
@@ -270,8 +288,14 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   int hex, hey;
   TL::halo_cell(tid < TL::NH ? tid : 0, hex, hey);
   const bool has_halo = tid < TL::NH;
-  const unsigned hcol = (unsigned)((x0 + hex - 2 + nx) % nx + nx * wrapn(y0 + hey - 2, ny));
+  const int hxc = (x0 + hex - 2 + nx) % nx, hyc = wrapn(y0 + hey - 2, ny);
+  const unsigned hcol = (unsigned)(hxc + nx * hyc);
   const unsigned hcolb = hcol * ES;
+  // a cell's byte offset and those of its x - 1 and x + 1 columns: an
+  // x-deferred input holds direction i of the cell at column x - c_ix
+  const unsigned colb3[3] = {colb + (unsigned)dxm, colb, colb + (unsigned)dxp};
+  const unsigned hcolb3[3] = {(unsigned)(wrapn(hxc - 1, nx) + nx * hyc) * ES, hcolb,
+                              (unsigned)(wrapn(hxc + 1, nx) + nx * hyc) * ES};
   const int he = hey * EX + hex;
   int rdir;
   const int ridx = TL::receiver(hex, hey, rdir);
@@ -320,26 +344,27 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
   // with 16 rows or FP64 the registers are not there and planes load in place
   constexpr bool PF = TY <= 8 && sizeof(C) == 4;
   C pfi[26], pfh[26];
-  auto load_f = [&](int zn, unsigned off, C* l) {
+  auto load_f = [&](int zn, const unsigned* o3, C* l) {
     const S* fz = fA + PS * 19 * zn;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) l[i] = ld_at(fz, F19, off, i * PB);
+    for (int i = 0; i < 19; ++i) l[i] = ld_at(fz, F19, o3[INP ? 1 - CX[i] : 1], i * PB);
   };
   auto load_g = [&](int zn, unsigned off, C* l) {
     const S* gz = gA + PS * 7 * zn;
 #pragma unroll
     for (int i = 0; i < 7; ++i) l[19 + i] = ld_at(gz, G7, off, i * PB);
   };
-  auto load_cell = [&](int zn, unsigned off, C* l) {
-    load_f(zn, off, l);
-    load_g(zn, off, l);
+  auto load_cell = [&](int zn, const unsigned* o3, C* l) {
+    load_f(zn, o3, l);
+    load_g(zn, o3[1], l);
   };
   // lanes without a halo cell load from beyond the descriptor range: the
   // hardware returns 0 without a memory access, and the load count stays
   // the same on every path (the compiler then waits only for these loads)
-  const unsigned hcolb_pf = has_halo ? hcolb : 0xFFFFFF00u;
+  const unsigned hcolb_pf[3] = {has_halo ? hcolb3[0] : 0xFFFFFF00u, has_halo ? hcolb : 0xFFFFFF00u,
+                                has_halo ? hcolb3[2] : 0xFFFFFF00u};
   auto prefetch = [&](int zn) {
-    load_cell(zn, colb, pfi);
+    load_cell(zn, colb3, pfi);
     load_cell(zn, hcolb_pf, pfh);
   };
 #pragma unroll
@@ -382,7 +407,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
     if constexpr (!PF) {
       if (exists) {
         C li[26];
-        load_cell(zp, colb, li);
+        load_cell(zp, colb3, li);
 #pragma unroll
         for (int i = 0; i < 19; ++i) fb[i] = li[i];
 #pragma unroll
@@ -403,7 +428,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
         // priority 1, so that they reach the memory path ahead of arithmetic
         // of the other wave on the SIMD
         __builtin_amdgcn_s_setprio(1);
-        load_f(p + 1, colb, pfi);
+        load_f(p + 1, colb3, pfi);
         __builtin_amdgcn_s_setprio(0);
         next_loaded = true;
       } else if (p < p_end && plane_of(p + 1, zn)) {
@@ -475,7 +500,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       if (has_halo) {
         if constexpr (!PF) {
           C lh[26];
-          load_cell(zp, hcolb, lh);
+          load_cell(zp, hcolb3, lh);
 #pragma unroll
           for (int i = 0; i < 19; ++i) hv[i] = lh[i];
 #pragma unroll
@@ -616,19 +641,21 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
             __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int i = 0; i < kEarlyF; ++i)
-              st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+              st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(OUTP ? 0 : CX[i], CY[i]), i * PB, fa[i]);
             __builtin_amdgcn_s_setprio(0);
           } else if (!(a.zbound && (lo_out || hi_out))) {
 #pragma unroll
             for (int i = 0; i < 19; ++i)
-              st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+              st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(OUTP ? 0 : CX[i], CY[i]), i * PB, fa[i]);
           } else {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
               const bool out = (CZ[i] < 0 && lo_out) || (CZ[i] > 0 && hi_out);
               if (out) {
-                if (!pres_q) st_at(p0, F19, colb, opp19(i) * PB, fa[i]);
-              } else st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+                // bounce-back: f_opp(i)(x) = f*_i(x), x-deferred at column x + c_ix
+                if (!pres_q) st_at(p0, F19, OUTP ? nb_off(CX[i], 0) : colb, opp19(i) * PB, fa[i]);
+              } else
+                st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(OUTP ? 0 : CX[i], CY[i]), i * PB, fa[i]);
             }
           }
         }
@@ -664,7 +691,7 @@ __global__ void __launch_bounds__(FTX * TY) k_fused(const S* __restrict__ fA, co
       if (act) {
 #pragma unroll
         for (int i = kEarlyF; i < 19; ++i)
-          st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(CX[i], CY[i]), i * PB, fa[i]);
+          st_at(CZ[i] < 0 ? pm : (CZ[i] > 0 ? pp : p0), F19, nb_off(OUTP ? 0 : CX[i], CY[i]), i * PB, fa[i]);
       }
       __builtin_amdgcn_s_setprio(0);
     }
@@ -835,10 +862,11 @@ struct FusedImpl {
   // per workgroup (0: all); xcd_map: give each XCD a 2 x 4 block of tiles
   // fo: NULL for a plain step; otherwise the step also writes the fields of
   // its start state there and completes the start state's face-plane g in
-  // place (8-row tiles)
+  // place (8-row tiles).  xmode: x-deferred streaming of the input (bit 0)
+  // and of the output (bit 1), for plain steps on whole 8-row tiles
   static hipError_t step(const lbm_params& p, const Phys<C>& ph, hipStream_t stream, const S* fA, const S* gA, S* fB,
                          S* gB, const double* Tw0, const double* Tw1, int* flag, int ty, int chunk_planes,
-                         bool xcd_map, const FusedFields<C>* fo = nullptr) {
+                         bool xcd_map, const FusedFields<C>* fo = nullptr, int xmode = 0) {
     FusedArgs<C> a;
     a.ph = ph;
     a.nx = p.nx;
@@ -864,6 +892,7 @@ struct FusedImpl {
     a.fo = fo ? *fo : FusedFields<C>{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     a.g_face = const_cast<S*>(gA);
     const bool out = a.zpres[0] || a.zpres[1];
+    if (xmode != 0 && (fo || TY != 8 || p.nx % FTX != 0 || xmode < 0 || xmode > 3)) return hipErrorInvalidValue;
     if (fo) {
       // the same instantiation as the plain step of this grid, plus the
       // field stores (the stores only read values the step computes anyway,
@@ -884,12 +913,12 @@ struct FusedImpl {
       if (out) return launch_rag<true>(a, nchunks, stream, fA, gA, fB, gB);
       return launch_rag<false>(a, nchunks, stream, fA, gA, fB, gB);
     }
-    if (out) return launch<true>(a, TY, nchunks, stream, fA, gA, fB, gB);
-    return launch<false>(a, TY, nchunks, stream, fA, gA, fB, gB);
+    if (out) return launch<true>(a, TY, nchunks, stream, fA, gA, fB, gB, xmode);
+    return launch<false>(a, TY, nchunks, stream, fA, gA, fB, gB, xmode);
   }
   template <bool OUT>
   static hipError_t launch(const FusedArgs<C>& a, int TY, int nchunks, hipStream_t stream, const S* fA, const S* gA,
-                           S* fB, S* gB) {
+                           S* fB, S* gB, int xmode) {
     if constexpr (sizeof(S) <= 4) {
       if (TY == 16) {
         hipLaunchKernelGGL((k_fused<S, 16, OUT, false>), dim3(a.ntiles * nchunks), dim3(FTX * 16), 0, stream, fA,
@@ -897,8 +926,25 @@ struct FusedImpl {
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_fused<S, 8, OUT, false>), dim3(a.ntiles * nchunks), dim3(FTX * 8), 0, stream, fA, gA, fB,
-                       gB, a);
+    const dim3 grid(a.ntiles * nchunks), block(FTX * 8);
+    if constexpr (sizeof(S) == 8) {
+      switch (xmode) {
+        case 1:
+          hipLaunchKernelGGL((k_fused<S, 8, OUT, false, false, 1>), grid, block, 0, stream, fA, gA, fB, gB, a);
+          return hipGetLastError();
+        case 2:
+          hipLaunchKernelGGL((k_fused<S, 8, OUT, false, false, 2>), grid, block, 0, stream, fA, gA, fB, gB, a);
+          return hipGetLastError();
+        case 3:
+          hipLaunchKernelGGL((k_fused<S, 8, OUT, false, false, 3>), grid, block, 0, stream, fA, gA, fB, gB, a);
+          return hipGetLastError();
+        default:
+          break;
+      }
+    } else if (xmode != 0) {
+      return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((k_fused<S, 8, OUT, false>), grid, block, 0, stream, fA, gA, fB, gB, a);
     return hipGetLastError();
   }
   template <bool OUT>

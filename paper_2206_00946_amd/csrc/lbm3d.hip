@@ -83,6 +83,9 @@ struct lbm_ctx {
   int fused_chunk = 0;  // z planes per workgroup of the fused kernel (0: all)
   int fused_ty = 8;     // tile height of the fused kernel
   bool fused_map = false;  // fused kernel: each XCD a 2 x 4 block of tiles
+  // the steps of one lbm_step call pass x-deferred states to each other
+  // (FP64 storage, whole 8-row tiles of the fused kernel)
+  bool fused_xdefer = false;
   int device = 0;  // HIP device current at lbm_create
   std::string err;
 };
@@ -294,11 +297,11 @@ struct Impl {
     return step_ref_to(ctx, fs, gs, fd, gd, ctx_fields(ctx));
   }
 
-  static hipError_t step_fused(lbm_ctx* ctx, const S* fs, const S* gs, S* fd, S* gd) {
+  static hipError_t step_fused(lbm_ctx* ctx, const S* fs, const S* gs, S* fd, S* gd, int xmode = 0) {
     const lbm_params& p = ctx->p;
     return FusedImpl<S>::step(p, phys_of<C>(p), ctx->stream, fs, gs, fd, gd, ctx->has_Tw[0] ? ctx->Tw[0] : nullptr,
                               ctx->has_Tw[1] ? ctx->Tw[1] : nullptr, ctx->flag, ctx->fused_ty, ctx->fused_chunk,
-                              ctx->fused_map);
+                              ctx->fused_map, nullptr, xmode);
   }
 
   // A single-pass step that also writes the fields of its start state into F
@@ -316,8 +319,11 @@ struct Impl {
     return ctx->fused_ok ? step_fused(ctx, fs, gs, fd, gd) : step_ref(ctx, fs, gs, fd, gd);
   }
 
-  static hipError_t step(lbm_ctx* ctx) {
-    hipError_t e = step_from(ctx, (S*)ctx->fA, (S*)ctx->gA, (S*)ctx->fB, (S*)ctx->gB);
+  // xmode (fused kernel, whole 8-row tiles): bit 0, the current state is
+  // x-deferred; bit 1, leave the next state x-deferred
+  static hipError_t step(lbm_ctx* ctx, int xmode = 0) {
+    hipError_t e = xmode ? step_fused(ctx, (S*)ctx->fA, (S*)ctx->gA, (S*)ctx->fB, (S*)ctx->gB, xmode)
+                         : step_from(ctx, (S*)ctx->fA, (S*)ctx->gA, (S*)ctx->fB, (S*)ctx->gB);
     if (e != hipSuccess) return e;
     std::swap(ctx->fA, ctx->fB);
     std::swap(ctx->gA, ctx->gB);
@@ -742,6 +748,10 @@ lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_by
       if (ev[0] == '0') ctx->fused_ok = false;
     }
     if (const char* ev = std::getenv("LBM_FUSED_CHUNK")) ctx->fused_chunk = std::max(1, std::atoi(ev));
+    ctx->fused_xdefer = ctx->fused_ok && ctx->fused_ty == 8 && p->nx % FTX == 0 && p->precision == LBM_FP64;
+    if (const char* ev = std::getenv("LBM_FUSED_XDEFER")) {
+      if (ev[0] == '0') ctx->fused_xdefer = false;
+    }
   }
   hipError_t e = hipMemsetAsync(ctx->flag, 0, 64, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -884,8 +894,12 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps) {
   if (!ctx) return LBM_EINVAL;
   if (nsteps < 0) { ctx->err = "nsteps must be >= 0"; return LBM_EINVAL; }
   if (!ctx->initialised) { ctx->err = "lbm_step before lbm_init"; return LBM_ESTATE; }
+  // between the steps of one call the D3Q19 populations may stay x-deferred
+  // (streamed in y and z; the next step reads them shifted in x); the state
+  // the call leaves is the ordinary one
   for (int s = 0; s < nsteps; ++s) {
-    HIPCHK(ctx, dispatch(ctx, [&](auto impl) { return decltype(impl)::step(ctx); }));
+    const int xmode = ctx->fused_xdefer ? (s > 0 ? 1 : 0) | (s + 1 < nsteps ? 2 : 0) : 0;
+    HIPCHK(ctx, dispatch(ctx, [&](auto impl) { return decltype(impl)::step(ctx, xmode); }));
     ctx->step++;
   }
   int flag = 0;

@@ -524,6 +524,52 @@ def test_fused_xcd_block_mapping_is_bitwise_the_same(P, monkeypatch):
         assert np.array_equal(a, b), what
 
 
+@pytest.mark.parametrize("chunk", ["", "5"])
+@pytest.mark.parametrize("name", ["droplet_periodic_128x16x24", "blobs_closed_64x32x40", "wetting_64x16x24",
+                                  "heated_wall_64x16x24", "outlet_below_64x16x24", "open_z_64x16x32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_step_call_is_bitwise_single_steps(P, prec, name, chunk, monkeypatch):
+    """Within one multi-step call the single-pass kernel passes x-deferred
+    states between its steps with FP64 storage (streamed in y and z,
+    finished in x by the next step's loads); every cell is computed from the
+    same values, so k steps in
+    one call leave bitwise the populations of k one-step calls, also with the
+    z range cut into 5-plane chunks (boundary planes inside the march).  Slots
+    no step defines (fed from beyond a bounded face) are left out."""
+    if chunk:
+        monkeypatch.setenv("LBM_FUSED_CHUNK", chunk)
+    w = FUSED[name]()
+    _log(f"[x-deferred] {name} {prec} chunk={chunk or 'all'}")
+    out = []
+    for calls in ((7,), (1,) * 7):
+        sim = P.from_workload(w, precision=prec)
+        for k in calls:
+            sim.step(k)
+        out.append(sim.populations())
+        sim.close()
+    masks = _defined_slots(w)
+    for a, b, m, what in zip(out[0], out[1], masks, ("f", "g")):
+        m = np.broadcast_to(m[:, :, None, None], a.shape)
+        assert np.array_equal(a[m], b[m]), what
+
+
+def test_multi_step_call_can_switch_off_x_deferral(P, monkeypatch):
+    """LBM_FUSED_XDEFER=0 keeps the ordinary state between steps: the same
+    result bitwise."""
+    w = FUSED["heated_wall_64x16x24"]()
+    out = []
+    for xd in ("1", "0"):
+        monkeypatch.setenv("LBM_FUSED_XDEFER", xd)
+        sim = P.from_workload(w, precision="fp64")
+        sim.step(9)
+        out.append(sim.populations())
+        sim.close()
+    masks = _defined_slots(w)
+    for a, b, m, what in zip(out[0], out[1], masks, ("f", "g")):
+        m = np.broadcast_to(m[:, :, None, None], a.shape)
+        assert np.array_equal(a[m], b[m]), what
+
+
 # ---------------------------------------------------------------- vartheta = 1
 
 def _theta1(w):
