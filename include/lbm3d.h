@@ -168,7 +168,9 @@ lbm_status lbm_set_kappa(lbm_ctx* ctx, double kappa_w);
  * work is enqueued on the ctx stream;
  * the call synchronises once at the end to read the non-physical-state flag
  * and returns LBM_ENONPHYS if any step met rho <= 0, rho*b >= 1, T <= 0,
- * a negative psi radicand or a NaN (the state stays readable). */
+ * a negative psi radicand or a NaN (the state stays readable).  If a HIP
+ * call fails part-way (LBM_EHIP) the state is unspecified: between the steps
+ * of one call the library may keep the populations in an internal layout. */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* rho, real velocity u (eq. (5); 3*cells, component-major) and T of the
