@@ -306,6 +306,11 @@ def main():
         r = time_precision(P, torch, w, prec, vsteps, max(2, args.warmup // 2))
         variants[prec] = dict(mlups=round(r["mlups"], 1), ms_per_step=round(r["ms_per_step"], 4),
                               alg_bytes_per_cell=ALG_BYTES[prec], roofline_frac=round(r["frac"], 4))
+        if prec == "fp64" and step_kernels(w) == "single-pass" and w["nx"] % 64 == 0:
+            # the timed steps run in one lbm_step call: FP64 steps pass
+            # x-deferred states to each other (the call starts from and
+            # leaves the ordinary state)
+            variants[prec]["streaming"] = "x-deferred between the steps of one call"
     accuracy = None
     if args.accuracy_steps:
         print(f"[bench] accuracy vs fp64 storage, {args.accuracy_steps} steps", file=sys.stderr, flush=True)
