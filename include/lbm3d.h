@@ -134,13 +134,14 @@ lbm_status lbm_required_bytes(const lbm_params* p, size_t* state_bytes, size_t* 
  * (walls on x/y faces) give LBM_EUNSUPPORTED.
  * A step runs as one single-pass kernel launch when x and y are periodic, z
  * is periodic or has a wall or pressure outlet on each of its two faces,
- * nx % 64 == 0, ny % 8 == 0, nz >= 4 and
- * theta_corr = 0; otherwise as four launches of the general kernels (same
- * results to rounding).  Environment overrides read when the context is
- * created, for tests and measurements: LBM_FUSED=0 forces the general kernels,
- * LBM_FUSED_CHUNK=n cuts the z march of the single-pass kernel into n-plane
- * chunks, LBM_FUSED_TY=16 selects 16-row tiles (FP32/FP16/BF16),
- * LBM_FUSED_MAP=1 gives each XCD a 2 x 4 block of tiles. */
+ * nx >= 8, ny % 8 == 0, nz >= 4 and theta_corr = 0; otherwise as four
+ * launches of the general kernels (same results to rounding).  Environment
+ * overrides read when the context is created, for tests and measurements:
+ * LBM_FUSED=0 forces the general kernels, LBM_FUSED_CHUNK=n cuts the z march
+ * of the single-pass kernel into n-plane chunks, LBM_FUSED_TY=16 selects
+ * 16-row tiles (FP32/FP16/BF16, nx % 64 == 0, ny % 16 == 0), LBM_FUSED_MAP=1
+ * gives each XCD a 2 x 4 block of tiles, LBM_FUSED_XDEFER=0 keeps the
+ * ordinary state between the FP64 steps of one lbm_step call. */
 lbm_status lbm_create(const lbm_params* p, void* device_buffer, size_t buffer_bytes,
                       void* hip_stream, lbm_ctx** out);
 
