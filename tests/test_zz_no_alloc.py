@@ -38,12 +38,14 @@ def _adjoint(P, w, prec, nsteps, noalloc):
     return J, grad, dk, d, fields
 
 
-# (name, workload, storage, steps): the second request is smaller than the first
+# (name, workload, storage, steps): each request is smaller than the one before
 CALLS = [
     ("heated_wall_64x16x12 fp64, 8 steps",
      lambda: synth.heated_wall(nx=64, ny=16, nz=12, R0=5.0, Tw_jitter=0.02, seed=5, kappa_w=0.2), "fp64", 8),
     ("heated_wall_64x8x8 fp64, 5 steps",
      lambda: synth.heated_wall(nx=64, ny=8, nz=8, R0=3.0, Tw_jitter=0.02, seed=6, kappa_w=0.3), "fp64", 5),
+    ("heated_wall_64x8x8 fp32, 4 steps",
+     lambda: synth.heated_wall(nx=64, ny=8, nz=8, R0=3.0, Tw_jitter=0.02, seed=7, kappa_w=0.3), "fp32", 4),
 ]
 
 
