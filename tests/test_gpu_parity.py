@@ -541,16 +541,17 @@ def test_multi_step_call_is_bitwise_single_steps(P, prec, name, chunk, monkeypat
     w = FUSED[name]()
     _log(f"[x-deferred] {name} {prec} chunk={chunk or 'all'}")
     out = []
-    for calls in ((7,), (1,) * 7):
+    for calls in ((7,), (2, 5), (1,) * 7):
         sim = P.from_workload(w, precision=prec)
         for k in calls:
             sim.step(k)
         out.append(sim.populations())
         sim.close()
     masks = _defined_slots(w)
-    for a, b, m, what in zip(out[0], out[1], masks, ("f", "g")):
-        m = np.broadcast_to(m[:, :, None, None], a.shape)
-        assert np.array_equal(a[m], b[m]), what
+    for got in out[:2]:
+        for a, b, m, what in zip(got, out[2], masks, ("f", "g")):
+            m = np.broadcast_to(m[:, :, None, None], a.shape)
+            assert np.array_equal(a[m], b[m]), what
 
 
 def test_multi_step_call_can_switch_off_x_deferral(P, monkeypatch):
