@@ -38,6 +38,11 @@ int main() {
       {"plane_8192x4096_fp32", box(8192, 4096, 4, LBM_FP32_DEV, LBM_FACE_WALL)},
       {"plane_8192x4096_fp64", box(8192, 4096, 4, LBM_FP64, LBM_FACE_WALL)},
       {"plane_8192x8192_fp32", box(8192, 8192, 4, LBM_FP32_DEV, LBM_FACE_WALL)},
+      // the largest planes below the 32-bit offset limit and the next row up
+      {"limit_5184x5104_fp64", box(5184, 5104, 4, LBM_FP64, LBM_FACE_PERIODIC)},
+      {"over_5184x5112_fp64", box(5184, 5112, 4, LBM_FP64, LBM_FACE_PERIODIC)},
+      {"limit_7296x7256_fp32", box(7296, 7256, 4, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
+      {"over_7296x7264_fp32", box(7296, 7264, 4, LBM_FP32_DEV, LBM_FACE_PERIODIC)},
   };
   for (const Case& c : cases) std::printf("%s %d\n", c.name, lbm::fused_supported(c.p, 8) ? 1 : 0);
   // 16-row tiles: 32/16-bit storage only, ny a multiple of 16

@@ -19,6 +19,7 @@ EXPECTED = {
     "outlets_256x256x256_fp64": 1, "half_open_256x256x256_fp32": 0, "side_outlet_128x128x128_fp32": 0,
     "plane_4096x4096_fp64": 1, "plane_8192x4096_fp32": 1, "plane_8192x4096_fp64": 0,
     "plane_8192x8192_fp32": 0,
+    "limit_5184x5104_fp64": 1, "over_5184x5112_fp64": 0, "limit_7296x7256_fp32": 1, "over_7296x7264_fp32": 0,
     "ty16_512x512x384_fp32": 1, "ty16_512x512x384_fp64": 0, "ty16_64x8x8_fp32": 0,
     "ty16_ragged_96x16x8_fp32": 0,
     # z planes per workgroup: one round of 256 workgroups where the tiles

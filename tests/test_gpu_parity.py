@@ -302,6 +302,47 @@ def test_full_size_sampled(P, name, prec):
     _log(f"[full size] {name} {prec}: {len(pts)} cells ok")
 
 
+# the largest direction planes the single-pass kernel takes (its buffer
+# offsets are 32-bit: 19 planes of one level below 0xF0000000 bytes)
+LIMIT = {"fp64": (5184, 5104), "fp32": (7296, 7256)}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_largest_single_pass_planes(P, prec):
+    """A periodic 4-plane grid whose 19 direction planes of one level span
+    just under the single-pass kernel's 32-bit offset limit (4.02 of 4.03 GB;
+    one row more runs the general kernels, `test_fused_support.py`): two
+    steps in one call (FP64: x-deferred between them), compared at sampled
+    cells with the oracle run on the surrounding blocks."""
+    nx, ny = LIMIT[prec]
+    es = 8 if prec == "fp64" else 4
+    assert 19 * (nx * ny + 64) * es < 0xF0000000 <= 19 * (nx * (ny + 8) + 64) * es
+    k = 2
+    _log(f"[offset limit] {nx}x{ny}x4 {prec}: generating")
+    w = synth.droplet_periodic(nx=nx, ny=ny, nz=4, R0=300.0, W=5.0, noise=0.0,
+                               center=(nx / 2, ny / 2, 2.0))
+    rng = np.random.default_rng(13)
+    pts = [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(4))) for _ in range(4)]
+    pts += [(0, 0, 0), (nx - 1, ny - 1, 3), (nx - 1, 0, 1), (0, ny - 1, 2)]
+    pts += [(nx // 2 + 300, ny // 2, 1), (nx // 2, ny // 2 - 300, 2)]  # on the interface
+    _log(f"[offset limit] {nx}x{ny}x4 {prec}: GPU steps")
+    sim = P.from_workload(w, precision=prec)
+    sim.step(k)
+    rho, u, T = sim.fields()
+    sim.close()
+    del sim
+    tol_r, tol_u, tol_T = (TOL64, 1e-13, TOL64) if prec == "fp64" else (1e-5, 2e-6, 1e-5)
+    for (x, y, z) in pts:
+        b = sub_block(w, (x, y, z), half=6 * k + 4, margin=6 * k + 1)
+        ref = oracle_run(b, k, record=(k,))[k]
+        lx, ly, lz = b["local"]
+        er = abs(rho[z, y, x] - ref[0][lz, ly, lx]) / abs(ref[0][lz, ly, lx])
+        eT = abs(T[z, y, x] - ref[2][lz, ly, lx]) / abs(ref[2][lz, ly, lx])
+        eu = np.abs(u[:, z, y, x] - ref[1][:, lz, ly, lx]).max()
+        assert er < tol_r and eT < tol_T and eu < tol_u, ((x, y, z), er, eu, eT)
+    _log(f"[offset limit] {nx}x{ny}x4 {prec}: {len(pts)} cells ok")
+
+
 # ---------------------------------------------------------------- fused single-pass kernel
 
 def _closed(w):
